@@ -1,0 +1,229 @@
+"""FFT-EVP fixed-point solve of the oracle (test infrastructure only).
+
+One strain increment t -> t+dt (Sec. 2.1, Eq. 1-2; augmented Lagrangian of
+the nonlinear local equations, Sec. 2.1), written step by step:
+
+    E <- E_t with the strain-controlled components advanced by Edot*dt
+    e <- e_t + (E - E_t);  lam <- sigma_t
+    repeat:
+      (1) sigma = argmin Phi per voxel (local.local_solve);
+          eps = S:sigma + epsp_t + dt*epsdot_p(sigma)
+      (2) err_c  = rms|e - eps| / |E|
+          err_bc = |(Sigma* - <sigma>)_s| / |<sigma>|    (s: stress-controlled)
+          stop when both are below tol
+      (3) E_s += [(C0)_ss]^-1 (Sigma* - <sigma>)_s
+      (4) tau = sigma - C0:eps ; tau_hat = FFT(tau)
+      (5) e_hat = -Gamma0:tau_hat (C0^-1 at Nyquist), e_hat(0) = N^3 E;
+          e = IFFT(e_hat); lam = sigma
+    state update: epsp += dt*epsdot_p(sigma);
+                  rho  += dt*(k1 sqrt(rho) - k2 rho) * sum_a |gdot_a(sigma)|
+                  tauc  = tau0 + alpha*mu*b*sqrt(rho)
+
+The hardening law is a Kocks-Mecking storage/recovery law on one density
+per voxel; its storage and athermal-recovery terms play the roles of the
+lock-forming (c4) and athermal-annihilation (c5) terms of the SSD evolution
+(Sec. 2.2, Eq. 6), and the Taylor constant that of c1 in the passing stress
+(Sec. 2.2, Eq. 3). The plastic strain follows the first-order update stated
+after Eq. 1.
+
+Units: MPa, s, m, m^-2. Public arrays are plain components
+[11, 22, 33, 23, 13, 12], component-major, voxels ``[z][y][x]``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+from . import local as L
+from .crystal import voxel_material
+from .green import gamma_field, green_apply
+from .tensors import (isotropic_c4, mandel_to_voigt, voigt_to_mandel, c4_to_mandel)
+
+# cubic Cu elastic constants (MPa)
+CU = dict(C11=168400.0, C12=121400.0, C44=75400.0)
+
+
+@dataclass
+class Flow:
+    tau0: float = 5.0          # MPa
+    k1: float = 8.0e7          # 1/m
+    k2: float = 10.0           # -
+    n: float = 10.0            # rate exponent
+    gdot0: float = 1.0e-3      # 1/s
+    alpha: float = 0.5         # Taylor constant
+    mu: float = 47337.0        # MPa (Hill average shear modulus of Cu)
+    b: float = 2.56e-10        # m
+
+    def theta(self):
+        return np.array([self.tau0, self.k1, self.k2, self.n])
+
+    def with_theta(self, th):
+        return replace(self, tau0=float(th[0]), k1=float(th[1]), k2=float(th[2]),
+                       n=float(th[3]))
+
+
+@dataclass
+class Loading:
+    Edot: np.ndarray = field(default_factory=lambda: np.array([0, 0, -1e-3, 0, 0, 0.0]))
+    Sigma: np.ndarray = field(default_factory=lambda: np.zeros(6))
+    strain_ctrl: np.ndarray = field(default_factory=lambda: np.array([0, 0, 1, 0, 0, 0]))
+    dt: float = 2.0
+
+
+def default_c0(C11, C12, C44):
+    """Isotropic reference medium (lambda0, mu0): the crystal's bulk modulus and
+    1/16 of its Voigt-average shear modulus. The converged fields do not depend
+    on this choice; a shear modulus between the elastic and the viscoplastic
+    tangent moduli makes the iteration converge in tens of steps."""
+    K = (C11 + 2 * C12) / 3.0
+    mu = (C11 - C12 + 3 * C44) / 5.0 / 16.0
+    return K - 2.0 * mu / 3.0, mu
+
+
+class Oracle:
+    """Plain FP64 CPU implementation of the increment loop."""
+
+    def __init__(self, shape, quat, rho, C11=CU["C11"], C12=CU["C12"], C44=CU["C44"],
+                 flow: Flow | None = None, c0=None, plastic=True):
+        self.shape = tuple(int(s) for s in shape)
+        self.nvox = int(np.prod(self.shape))
+        self.flow = flow or Flow()
+        self.plastic = plastic
+        self.elastic = (C11, C12, C44)
+        self.C, self.S, self.m = voxel_material(quat, C11, C12, C44)
+        lam0, mu0 = c0 if c0 is not None else default_c0(C11, C12, C44)
+        self.c0 = (lam0, mu0)
+        self.C0_4 = isotropic_c4(lam0, mu0)
+        self.C0 = c4_to_mandel(self.C0_4)
+        self.C0inv = np.linalg.inv(self.C0)
+        self.rho = np.asarray(rho, dtype=np.float64).reshape(-1).copy()
+        self.epsp = np.zeros((self.nvox, 6))
+        self.sigma = np.zeros((self.nvox, 6))
+        self.e = np.zeros((self.nvox, 6))
+        self.E = np.zeros(6)
+        self.t = 0.0
+        self._G = None
+
+    # -- helpers ----------------------------------------------------------
+    def tauc(self, rho=None, flow=None):
+        f = flow or self.flow
+        r = self.rho if rho is None else rho
+        return f.tau0 + f.alpha * f.mu * f.b * np.sqrt(r)
+
+    def _gdot0(self):
+        return self.flow.gdot0 if self.plastic else 0.0
+
+    def local(self, lam, e, tauc, sig0=None, tol=1e-12):
+        f = self.flow
+        return L.local_solve(lam, e, self.epsp, tauc, self.S, self.m, self.C0inv,
+                             self._gdot0(), f.n, self._dt, sig0=sig0, tol=tol)
+
+    def strain(self, sig, tauc):
+        return L.constitutive_strain(sig, self.epsp, self.S, self.m, tauc,
+                                     self._gdot0(), self.flow.n, self._dt)
+
+    def spectral_update(self, tau, E):
+        """(4)-(5): compatible strain from the polarisation field (Mandel (M,6))."""
+        n0, n1, n2 = self.shape
+        t = tau.T.reshape(6, n2, n1, n0)
+        th = np.fft.fftn(t, axes=(1, 2, 3))
+        if self._G is None:
+            self._G = gamma_field(self.shape, self.C0_4, self.C0inv)
+        eh = green_apply(th, self._G, E)
+        e = np.fft.ifftn(eh, axes=(1, 2, 3))
+        return np.ascontiguousarray(e.real.reshape(6, -1).T)
+
+    # -- one increment ----------------------------------------------------
+    def increment(self, load: Loading, tol=1e-6, max_iter=1000, history=False):
+        self._dt = load.dt
+        sc = np.asarray(load.strain_ctrl).astype(bool)
+        s = ~sc
+        Sig_star = voigt_to_mandel(np.asarray(load.Sigma, dtype=np.float64))
+        E = self.E.copy()
+        E[sc] += voigt_to_mandel(np.asarray(load.Edot, dtype=np.float64))[sc] * load.dt
+        e = self.e + (E - self.E)[None, :]
+        lam = self.sigma.copy()
+        tauc = self.tauc()
+        C0ss_inv = np.linalg.inv(self.C0[np.ix_(s, s)]) if s.any() else None
+        hist = []
+        converged = False
+        for it in range(max_iter):
+            sig, nit, nfail = self.local(lam, e, tauc)
+            eps = self.strain(sig, tauc)
+            err_c = np.sqrt(np.mean(np.sum((e - eps) ** 2, axis=1))) / np.linalg.norm(E)
+            Sm = sig.mean(axis=0)
+            dS = (Sig_star - Sm)[s]
+            nS = np.linalg.norm(Sm)
+            nb = np.linalg.norm(dS)
+            err_bc = nb / nS if nS > 0 else (0.0 if nb == 0 else np.inf)
+            if history:
+                hist.append(dict(err_c=err_c, err_bc=err_bc, newton_max=int(nit.max()),
+                                 Sigma=mandel_to_voigt(Sm)))
+            if err_c < tol and err_bc < tol:
+                converged = True
+                break
+            if s.any():
+                E[s] += C0ss_inv @ dS
+            tau = sig - eps @ self.C0.T
+            e = self.spectral_update(tau, E)
+            lam = sig
+        iters = it + 1
+        # state update at the converged stress, density from the increment start
+        f = self.flow
+        _, gdot = L.slip_rates(sig, self.m, tauc, self._gdot0(), f.n)
+        self.epsp = self.epsp + load.dt * np.einsum("ma,mak->mk", gdot, self.m)
+        gsum = np.abs(gdot).sum(axis=1)
+        self.rho = self.rho + load.dt * (f.k1 * np.sqrt(self.rho) - f.k2 * self.rho) * gsum
+        self.sigma, self.e, self.E = sig, e, E
+        self.t += load.dt
+        rep = dict(iters=iters, converged=converged, err_c=err_c, err_bc=err_bc,
+                   Sigma=mandel_to_voigt(sig.mean(axis=0)), E=mandel_to_voigt(E),
+                   rho_mean=float(self.rho.mean()), newton_fail=nfail)
+        if history:
+            rep["history"] = hist
+        return rep
+
+    # -- public views (plain components, component-major) -----------------
+    def field(self, name):
+        a = {"sigma": self.sigma, "strain": self.e, "epsp": self.epsp}.get(name)
+        if a is not None:
+            return mandel_to_voigt(a.T)
+        if name == "rho":
+            return self.rho.copy()
+        raise KeyError(name)
+
+
+def run_path(oracle: Oracle, load: Loading, increments: int, tol=1e-6, max_iter=1000):
+    """Run ``increments`` increments; returns the list of reports."""
+    return [oracle.increment(load, tol=tol, max_iter=max_iter) for _ in range(increments)]
+
+
+def curve_loss(s33, target):
+    """L = (1/T) sum_t (<sigma33>_t - target_t)^2, stress in MPa."""
+    s33 = np.asarray(s33)
+    return float(np.mean((s33 - np.asarray(target)) ** 2))
+
+
+def stress_curve(shape, quat, rho, flow: Flow, load: Loading, increments, tol=1e-13,
+                 max_iter=5000, c0=None):
+    """<sigma33>_t for t = 1..T from a fresh state."""
+    o = Oracle(shape, quat, rho, flow=flow, c0=c0)
+    reps = run_path(o, load, increments, tol=tol, max_iter=max_iter)
+    return np.array([r["Sigma"][2] for r in reps]), reps
+
+
+def fd_gradient(shape, quat, rho, flow: Flow, load: Loading, increments, target,
+                rel_step=1e-5, tol=1e-13, c0=None):
+    """Central finite differences of the curve loss w.r.t. (tau0, k1, k2, n)."""
+    th = flow.theta()
+    g = np.zeros(4)
+    for k in range(4):
+        h = rel_step * abs(th[k])
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        sp, _ = stress_curve(shape, quat, rho, flow.with_theta(tp), load, increments, tol, c0=c0)
+        sm, _ = stress_curve(shape, quat, rho, flow.with_theta(tm), load, increments, tol, c0=c0)
+        g[k] = (curve_loss(sp, target) - curve_loss(sm, target)) / (2 * h)
+    return g
