@@ -1,0 +1,192 @@
+/*
+ * fftevp.h — C ABI of the MI355X FFT-EVP fixed-point solve.
+ *
+ * The library solves, at every strain increment, the small-strain
+ * elasto-viscoplastic problem of Zhao, Low, Wang & Niezgoda (Sec. 2.1):
+ *   - implicit Euler Hooke law  sigma = C(x):[eps - epsp_t - epsdot_p(sigma) dt]  (Eq. 1),
+ *   - plastic strain rate as a sum over slip systems  epsdot_p = sum_a m_a gdot_a  (Eq. 2),
+ *   - stress equilibrium and strain compatibility on a periodic voxel grid,
+ *     solved spectrally (FFT + Green operator of an isotropic reference medium)
+ *     with an augmented-Lagrangian treatment of the nonlinear local law (Sec. 2.1),
+ * with a power-law flow rule over the 12 FCC {111}<110> slip systems and a
+ * Kocks-Mecking law for one dislocation density per voxel (the storage and
+ * athermal-recovery terms of Eq. 6, Taylor hardening as in the passing stress
+ * of Eq. 3). Inputs follow the paper's statement of the problem: a periodic
+ * voxel grid, a lattice orientation and a dislocation density per voxel,
+ * cubic elastic constants, an applied macroscopic strain rate with
+ * stress-free lateral faces (simple compression, Sec. 3), and a time
+ * increment.
+ *
+ * Conventions
+ *   - Units: MPa, s, m, m^-2.
+ *   - Symmetric tensors at this boundary are plain components in the order
+ *     [11, 22, 33, 23, 13, 12] (tensor strain, not engineering shear).
+ *   - Fields are device pointers, FP64, component-major and voxel-minor:
+ *     element (c, z, y, x) at c*V + (z*n1 + y)*n0 + x, V = n0*n1*n2.
+ *   - Quaternions (w, x, y, z), unit, rotate crystal -> sample (active).
+ *   - Every call is enqueued on the stream given to fftevp_create; calls that
+ *     return host scalars synchronise that stream.
+ *   - The caller owns every pointer it passes; fftevp_set_* copy their input.
+ *     The context owns its device workspaces.
+ *   - One context per host thread at a time; contexts are independent.
+ *   - The library never aborts: failures return a negative status and set
+ *     the text returned by fftevp_last_error.
+ */
+#ifndef FFTEVP_H
+#define FFTEVP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFTEVP_OK = 0,
+  FFTEVP_NOT_CONVERGED = 1, /* result reported, state NOT committed           */
+  FFTEVP_EINVAL = -1,       /* bad argument; nothing was changed               */
+  FFTEVP_ENOMEM = -2,       /* device allocation failed                        */
+  FFTEVP_EHIP = -3,         /* a HIP runtime call failed                       */
+  FFTEVP_ENONFINITE = -4,   /* residual or average not finite; not committed   */
+  FFTEVP_ELOCAL = -5,       /* a voxel's Newton solve did not converge         */
+  FFTEVP_ESTATE = -6        /* call out of order (e.g. step before set_*)      */
+} fftevp_status;
+
+typedef enum { FFTEVP_FP64 = 0, FFTEVP_MIXED = 1 } fftevp_precision;
+
+typedef enum {
+  FFTEVP_FIELD_SIGMA = 0,       /* committed stress, 6 comps                      */
+  FFTEVP_FIELD_STRAIN = 1,      /* committed compatible strain e, 6 comps         */
+  FFTEVP_FIELD_EPS_P = 2,       /* plastic strain, 6 comps                        */
+  FFTEVP_FIELD_RHO = 3,         /* dislocation density, 1 comp                    */
+  FFTEVP_FIELD_SIGMA_ITER = 4,  /* stress of the latest iteration, 6 comps        */
+  FFTEVP_FIELD_STRAIN_ITER = 5  /* compatible strain after the latest iteration   */
+} fftevp_field;
+
+typedef struct fftevp_ctx fftevp_ctx;
+
+/* Cubic elastic constants in the crystal frame (MPa). Eq. 1's C(x) is this
+ * tensor rotated by the voxel orientation. Requires C11 > |C12|,
+ * C11 + 2 C12 > 0, C44 > 0. */
+typedef struct { double C11, C12, C44; } fftevp_cubic;
+
+/* Flow and hardening parameters.
+ *   gdot_a = gdot0 |tau_a / tauc|^n sign(tau_a),   tau_a = m_a : sigma
+ *   tauc   = tau0 + alpha mu b sqrt(rho)
+ *   d rho / dt = (k1 sqrt(rho) - k2 rho) sum_a |gdot_a|
+ * (tau0, k1, k2, n) are the parameters the adjoint differentiates.
+ * Requires n >= 1, gdot0 >= 0, tau0 > 0, alpha, mu, b >= 0, k1, k2 >= 0. */
+typedef struct {
+  double tau0, k1, k2, n;       /* MPa, 1/m, -, -  */
+  double gdot0, alpha, mu, b;   /* 1/s, -, MPa, m  */
+} fftevp_flow;
+
+/* Macroscopic loading for the next increments. Component c is strain
+ * controlled when strain_ctrl[c] != 0 (its mean strain advances by
+ * Edot[c]*dt per increment), otherwise stress controlled (mean stress held
+ * at Sigma[c]). At least one component must be strain controlled. dt > 0. */
+typedef struct {
+  double Edot[6];
+  double Sigma[6];
+  int strain_ctrl[6];
+  double dt;
+} fftevp_loading;
+
+/* Solver options. A zero field selects the default shown.
+ *   tol        stop when err_c < tol and err_bc < tol          (1e-6)
+ *   max_iter   fixed-point iterations per increment            (1000)
+ *   newton_max Newton iterations per voxel and iteration       (50)
+ *   c0_lambda, c0_mu  isotropic reference medium (MPa). Default: bulk
+ *              modulus of the crystal, shear modulus 1/16 of the crystal's
+ *              Voigt average. Both must be given together. */
+typedef struct {
+  double tol;
+  int max_iter;
+  int newton_max;
+  double c0_lambda, c0_mu;
+} fftevp_opts;
+
+/* Per-increment report.
+ *   err_c   rms_x |e - eps| / |E|   (compatibility vs. constitutive strain)
+ *   err_bc  |(Sigma* - <sigma>)_s| / |<sigma>| over stress-controlled comps
+ *   Sigma   volume-averaged stress of the last iterate, E the mean strain
+ *   rho_mean mean density after the state update (unchanged if not committed) */
+typedef struct {
+  int iters, newton_max_seen, newton_failed;
+  double err_c, err_bc, Sigma[6], E[6], rho_mean;
+} fftevp_report;
+
+/* Create a context for an n0 x n1 x n2 grid (x, y, z), each a power of two
+ * in [8, 512]. hip_stream is a hipStream_t (NULL: the null stream).
+ * On success *out owns all device workspaces. */
+fftevp_status fftevp_create(int n0, int n1, int n2, fftevp_precision precision,
+                            void* hip_stream, fftevp_ctx** out);
+fftevp_status fftevp_destroy(fftevp_ctx* ctx);
+
+/* Elastic constants and flow/hardening parameters (Eq. 1-3, 6 roles above).
+ * May be called again between increments (e.g. to change the parameters). */
+fftevp_status fftevp_set_material(fftevp_ctx* ctx, const fftevp_cubic* cubic,
+                                  const fftevp_flow* flow);
+
+/* Per-voxel orientation and density (device, FP64): quat [4][V], rho [V].
+ * Validates: quaternions finite with |q| within 1e-6 of 1, rho finite and
+ * > 0; EINVAL otherwise. Resets the mechanical state (stress, strain,
+ * plastic strain, mean strain, time) to zero. */
+fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat_dev,
+                                        const double* rho_dev);
+
+fftevp_status fftevp_set_loading(fftevp_ctx* ctx, const fftevp_loading* loading);
+
+/* One strain increment: the fixed-point solve, then the explicit update of
+ * plastic strain and density at the converged stress (Eq. 1 first-order
+ * update; hardening law above). Returns OK, NOT_CONVERGED (max_iter reached:
+ * state kept from before the call), ENONFINITE, or ELOCAL (converged but
+ * some voxel Newton solves hit newton_max; state committed). out may be NULL. */
+fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_report* out);
+
+/* Copy a field (fftevp_field) into dst_dev (device, FP64, [ncomp][V]). */
+fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst_dev);
+
+/* Opaque device snapshot of the committed state (plastic strain, density,
+ * stress, compatible strain, mean strain, time). Buffers are device memory of
+ * fftevp_state_bytes() bytes owned by the caller. Loading a snapshot makes
+ * the following increments bit-identical to those run after the save. */
+size_t fftevp_state_bytes(const fftevp_ctx* ctx);
+fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst_dev);
+fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src_dev);
+
+/* Adjoint of one increment (reverse mode through the converged fixed point).
+ * state_before / state_after: snapshots taken before and after the increment
+ * (same loading and parameters as when it ran). dL_dSigma_mean: derivative of
+ * the loss w.r.t. the increment's volume-averaged stress (plain comps; only
+ * strain-controlled components matter, the others are fixed by the loading).
+ * adj_state_dev (device, caller-owned, fftevp_adjoint_bytes() bytes, zero it
+ * before the last increment): adjoint of the state after the increment on
+ * entry, adjoint of the state before it on return. dL_dtheta[4] (host,
+ * d/d(tau0, k1, k2, n)) is accumulated. The implicit linear problem is
+ * solved with the same spectral iteration, to opts->tol. */
+size_t fftevp_adjoint_bytes(const fftevp_ctx* ctx);
+fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
+                                       const void* state_before_dev,
+                                       const void* state_after_dev,
+                                       const double dL_dSigma_mean[6],
+                                       void* adj_state_dev, double dL_dtheta[4]);
+
+/* Kernel timing (diagnostics). When enabled, every kernel the solver launches
+ * is bracketed by HIP events on the context's stream, and the durations of
+ * launches that did work (not those skipped after convergence) are summed per
+ * kernel class: 0 local solve + x-FFTs, 1 reduction/stop test, 2 forward
+ * y-FFT, 3 z-FFT + Green operator, 4 inverse y-FFT, 5 end-of-increment update,
+ * 6 adjoint set-up. fftevp_get_profile copies the sums (ms) and launch counts
+ * into caller arrays of FFTEVP_NPROF entries and, if reset != 0, clears them. */
+#define FFTEVP_NPROF 7
+fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int enable);
+fftevp_status fftevp_get_profile(fftevp_ctx* ctx, double* ms, long long* launches, int reset);
+
+const char* fftevp_status_string(fftevp_status status);
+const char* fftevp_last_error(const fftevp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTEVP_H */

@@ -1,0 +1,776 @@
+// C ABI of the FFT-EVP solve: context, workspaces, increment driver,
+// field export and state snapshots. See include/fftevp.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fftevp.h"
+#include "kernels.h"
+
+using namespace fftevp;
+
+namespace {
+
+constexpr double kSnapMagic = 5.09049531e7;  // tags a state snapshot
+constexpr int kHeader = 32;                  // doubles in a snapshot header
+
+struct Bufs {
+  void* quat = nullptr;    // [4][V]
+  void* rho = nullptr;     // [V]
+  void* epsp = nullptr;    // [6][V]
+  void* sig[2] = {};       // committed / working stress, [6][V]
+  void* emain[3] = {};     // x-half-spectra of strain, [6][V/2] complex
+  void* enyq[3] = {};      // x-Nyquist planes, [6][n1 n2]
+  void* tmain = nullptr;   // polarisation spectra, [6][V/2] complex
+  void* tw[3] = {};        // twiddles per axis
+  // adjoint workspaces (allocated on first use)
+  void* a_eta = nullptr;   // eigenstrain of the adjoint solve, [6][V]
+  void* a_sigt = nullptr;  // forward stress of the increment, [6][V]
+  void* a_rho = nullptr;   // density at the start of the increment, [V]
+};
+
+}  // namespace
+
+struct fftevp_ctx {
+  int n0 = 0, n1 = 0, n2 = 0;
+  size_t V = 0, planes = 0;
+  fftevp_precision prec = FFTEVP_FP64;
+  size_t tsize = 8;
+  hipStream_t stream = nullptr;
+  bool have_mat = false, have_micro = false, have_load = false;
+  fftevp_cubic cubic{};
+  fftevp_flow flow{};
+  fftevp_loading load{};
+  Bufs b;
+  int sc = 0, sw = 1;  // committed / working stress buffer
+  int ec = 0;          // committed strain buffer
+  int e_last = 0;      // strain buffer written by the latest iteration
+  double* partial = nullptr;
+  int local_nb = 0, red_nb = 0;
+  Ctl* ctl = nullptr;
+  Ctl* ctl_h = nullptr;  // pinned
+  double* red2 = nullptr;
+  double* red2_h = nullptr;  // pinned
+  double E[6] = {0, 0, 0, 0, 0, 0};  // committed macroscopic strain (Mandel)
+  double t = 0.0;
+  double inc = 0.0;
+  int last_iters = 0;
+  std::string err;
+  // kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  struct Rec {
+    int cls, iter;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  double prof_ms[FFTEVP_NPROF] = {0};
+  long long prof_n[FFTEVP_NPROF] = {0};
+};
+
+namespace {
+
+const double kR2 = 1.41421356237309504880;
+
+fftevp_status fail(fftevp_ctx* c, fftevp_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, FFTEVP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+hipError_t ev_pair(fftevp_ctx* c, hipEvent_t* a, hipEvent_t* b) {
+  while (c->evpool.size() < c->evused + 2) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    c->evpool.push_back(e);
+  }
+  *a = c->evpool[c->evused++];
+  *b = c->evpool[c->evused++];
+  return hipSuccess;
+}
+
+// Launch through f(), bracketed by events when profiling; iter < 0 marks a
+// launch that always does work.
+template <typename F>
+hipError_t timed(fftevp_ctx* c, int cls, int iter, F&& f) {
+  if (!c->prof) return f();
+  hipEvent_t a, b;
+  hipError_t e = ev_pair(c, &a, &b);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(a, c->stream)) != hipSuccess) return e;
+  if ((e = f()) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, c->stream)) != hipSuccess) return e;
+  c->recs.push_back({cls, iter, a, b});
+  return hipSuccess;
+}
+
+// After a stream synchronisation: accumulate the launches that did work.
+// Iteration i ran its local solve and reduction if i < iters, and its
+// spectral passes if it did not stop (i < iters - 1, or i < iters when the
+// loop ended without converging).
+hipError_t harvest(fftevp_ctx* c, int iters, bool stopped) {
+  for (const auto& r : c->recs) {
+    bool did = r.iter < 0;
+    if (r.iter >= 0) {
+      if (r.cls <= 1) did = r.iter < iters;
+      else did = r.iter < (stopped ? iters - 1 : iters);
+    }
+    if (!did) continue;
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return e;
+    c->prof_ms[r.cls] += ms;
+    c->prof_n[r.cls] += 1;
+  }
+  c->recs.clear();
+  c->evused = 0;
+  return hipSuccess;
+}
+
+bool pow2_in_range(int n) { return n >= 8 && n <= 512 && (n & (n - 1)) == 0; }
+
+void to_mandel(const double* p, double* m) {
+  for (int k = 0; k < 6; ++k) m[k] = k < 3 ? p[k] : kR2 * p[k];
+}
+void to_plain(const double* m, double* p) {
+  for (int k = 0; k < 6; ++k) p[k] = k < 3 ? m[k] : m[k] / kR2;
+}
+
+struct C0 {
+  double lam, mu;
+};
+
+C0 reference_medium(const fftevp_ctx* ctx, const fftevp_opts* o) {
+  if (o && o->c0_mu > 0.0) return {o->c0_lambda, o->c0_mu};
+  const double K = (ctx->cubic.C11 + 2.0 * ctx->cubic.C12) / 3.0;
+  const double muV = (ctx->cubic.C11 - ctx->cubic.C12 + 3.0 * ctx->cubic.C44) / 5.0;
+  const double mu0 = muV / 16.0;
+  return {K - 2.0 * mu0 / 3.0, mu0};
+}
+
+Mat make_mat(const fftevp_ctx* ctx, C0 c0, double dt, double ntol, int newton_max) {
+  Mat m{};
+  const double C11 = ctx->cubic.C11, C12 = ctx->cubic.C12, C44 = ctx->cubic.C44;
+  const double den = (C11 - C12) * (C11 + 2.0 * C12);
+  m.s_d = (C11 + C12) / den;
+  m.s_o = -C12 / den;
+  m.s_s = 1.0 / (2.0 * C44);
+  const double K0 = c0.lam + 2.0 * c0.mu / 3.0;
+  m.c0l = c0.lam;
+  m.c0m = c0.mu;
+  m.ci_d = 1.0 / (9.0 * K0) + 1.0 / (3.0 * c0.mu);
+  m.ci_o = 1.0 / (9.0 * K0) - 1.0 / (6.0 * c0.mu);
+  m.ci_s = 1.0 / (2.0 * c0.mu);
+  m.a_d = m.s_d + m.ci_d;
+  m.a_o = m.s_o + m.ci_o;
+  m.a_s = m.s_s + m.ci_s;
+  m.c1 = dt * ctx->flow.gdot0;
+  m.n = ctx->flow.n;
+  const double nf = std::floor(m.n);
+  m.n_int = (nf == m.n && m.n >= 1.0 && m.n <= 64.0) ? (int)m.n : 0;
+  m.newton_max = newton_max;
+  m.ntol = ntol;
+  m.tau0 = ctx->flow.tau0;
+  m.taylor = ctx->flow.alpha * ctx->flow.mu * ctx->flow.b;
+  m.inv_n0 = 1.0 / ctx->n0;
+  return m;
+}
+
+// [(C0)_ss]^-1 over the stress-controlled components, embedded in 6x6 (Mandel)
+void c0ss_inverse(C0 c0, const int* strain_ctrl, double* out) {
+  double C[36] = {0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[6 * i + j] = c0.lam + (i == j ? 2.0 * c0.mu : 0.0);
+  for (int i = 3; i < 6; ++i) C[6 * i + i] = 2.0 * c0.mu;
+  int idx[6], ns = 0;
+  for (int k = 0; k < 6; ++k)
+    if (!strain_ctrl[k]) idx[ns++] = k;
+  std::vector<double> A(ns * 2 * ns, 0.0);
+  for (int i = 0; i < ns; ++i) {
+    for (int j = 0; j < ns; ++j) A[i * 2 * ns + j] = C[6 * idx[i] + idx[j]];
+    A[i * 2 * ns + ns + i] = 1.0;
+  }
+  for (int col = 0; col < ns; ++col) {  // Gauss-Jordan, SPD so no pivoting needed
+    const double p = A[col * 2 * ns + col];
+    for (int j = 0; j < 2 * ns; ++j) A[col * 2 * ns + j] /= p;
+    for (int r = 0; r < ns; ++r) {
+      if (r == col) continue;
+      const double f = A[r * 2 * ns + col];
+      for (int j = 0; j < 2 * ns; ++j) A[r * 2 * ns + j] -= f * A[col * 2 * ns + j];
+    }
+  }
+  for (int k = 0; k < 36; ++k) out[k] = 0.0;
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < ns; ++j) out[6 * idx[i] + idx[j]] = A[i * 2 * ns + ns + j];
+}
+
+template <typename T>
+std::vector<cx<T>> twiddles(int n) {
+  std::vector<cx<T>> w(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int m = 0; m < n; ++m) {
+    const long double a = 2.0L * pi * (long double)m / (long double)n;
+    w[m] = {(T)std::cos(a), (T)(-std::sin(a))};
+  }
+  return w;
+}
+
+template <typename T>
+fftevp_status alloc_all(fftevp_ctx* ctx) {
+  const size_t V = ctx->V, ts = sizeof(T);
+  auto al = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(*p, 0, bytes, ctx->stream);
+    return e;
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = al(&ctx->b.quat, 4 * V * ts);
+  if (e == hipSuccess) e = al(&ctx->b.rho, V * ts);
+  if (e == hipSuccess) e = al(&ctx->b.epsp, 6 * V * ts);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = al(&ctx->b.sig[i], 6 * V * ts);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = al(&ctx->b.emain[i], 6 * V * ts);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = al(&ctx->b.enyq[i], 6 * ctx->planes * ts);
+  if (e == hipSuccess) e = al(&ctx->b.tmain, 6 * V * ts);
+  const int ns[3] = {ctx->n0, ctx->n1, ctx->n2};
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    auto w = twiddles<T>(ns[i]);
+    e = hipMalloc(&ctx->b.tw[i], w.size() * sizeof(cx<T>));
+    if (e == hipSuccess)
+      e = hipMemcpy(ctx->b.tw[i], w.data(), w.size() * sizeof(cx<T>), hipMemcpyHostToDevice);
+  }
+  ctx->local_nb = local_blocks<T>(ctx->n0, ctx->n1, ctx->n2);
+  ctx->red_nb = 1024;
+  const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 2);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->partial, np * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->ctl, sizeof(Ctl));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->red2, 2 * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->red2_h, 2 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipErrorOutOfMemory) return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
+  if (e != hipSuccess) return fail(ctx, FFTEVP_EHIP, std::string("allocation: ") + hipGetErrorString(e));
+  return FFTEVP_OK;
+}
+
+void free_all(fftevp_ctx* ctx) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(ctx->b.quat);
+  f(ctx->b.rho);
+  f(ctx->b.epsp);
+  for (auto p : ctx->b.sig) f(p);
+  for (auto p : ctx->b.emain) f(p);
+  for (auto p : ctx->b.enyq) f(p);
+  f(ctx->b.tmain);
+  for (auto p : ctx->b.tw) f(p);
+  f(ctx->b.a_eta);
+  f(ctx->b.a_sigt);
+  f(ctx->b.a_rho);
+  f(ctx->partial);
+  f(ctx->ctl);
+  for (auto e : ctx->evpool) (void)hipEventDestroy(e);
+  f(ctx->red2);
+  if (ctx->ctl_h) (void)hipHostFree(ctx->ctl_h);
+  if (ctx->red2_h) (void)hipHostFree(ctx->red2_h);
+}
+
+// ---------------------------------------------------------------------------
+// one fixed-point iteration (forward or tangent) enqueued on the stream
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, const void* lam,
+                             void* sig_out, const void* epsp, const void* rho, const void* sig_t,
+                             const Mat& m, C0 c0, const FinArgs& fin, const double* dE) {
+  using C = cx<T>;
+  LocalArgs<T> la{};
+  la.e_main = (const C*)ctx->b.emain[in_buf];
+  la.e_nyq = (const T*)ctx->b.enyq[in_buf];
+  la.t_main = (C*)ctx->b.tmain;
+  la.e_nyq_next = (T*)ctx->b.enyq[out_buf];
+  la.lam = (const T*)lam;
+  la.sig = (T*)sig_out;
+  la.epsp = (const T*)epsp;
+  la.rho = (const T*)rho;
+  la.quat = (const T*)ctx->b.quat;
+  la.sig_t = (const T*)sig_t;
+  la.partial = ctx->partial;
+  la.ctl = ctx->ctl;
+  la.tw = (const C*)ctx->b.tw[0];
+  la.add_dE = (i == 0 && dE) ? 1 : 0;
+  for (int k = 0; k < 6; ++k) la.dE[k] = dE ? dE[k] : 0.0;
+  la.n1 = ctx->n1;
+  la.n2 = ctx->n2;
+  la.m = m;
+  hipError_t e = timed(ctx, 0, i, [&] { return launch_local<T, MODE>(ctx->n0, la, ctx->stream); });
+  if (e != hipSuccess) return e;
+  e = timed(ctx, 1, i, [&] { return launch_finalize(fin, ctx->stream); });
+  if (e != hipSuccess) return e;
+  YArgs<T> ya{(const C*)ctx->b.tmain, (C*)ctx->b.tmain, (const C*)ctx->b.tw[1], ctx->ctl, ctx->n0 / 2};
+  e = timed(ctx, 2, i, [&] { return launch_ypass<T, false>(ctx->n1, ctx->n2, ya, ctx->stream); });
+  if (e != hipSuccess) return e;
+  ZArgs<T> za{};
+  za.buf = (C*)ctx->b.tmain;
+  za.tw = (const C*)ctx->b.tw[2];
+  za.ctl = ctx->ctl;
+  za.h = ctx->n0 / 2;
+  za.n1 = ctx->n1;
+  za.inv_n0 = 1.0 / ctx->n0;
+  za.inv_n1 = 1.0 / ctx->n1;
+  za.inv_n2 = 1.0 / ctx->n2;
+  za.inv_ntot = 1.0 / (double)ctx->V;
+  za.c0l = c0.lam;
+  za.c0m = c0.mu;
+  za.ci_d = m.ci_d;
+  za.ci_o = m.ci_o;
+  za.ci_s = m.ci_s;
+  e = timed(ctx, 3, i, [&] { return launch_zgamma<T>(ctx->n2, za, ctx->stream); });
+  if (e != hipSuccess) return e;
+  YArgs<T> yi{(const C*)ctx->b.tmain, (C*)ctx->b.emain[out_buf], (const C*)ctx->b.tw[1], ctx->ctl,
+              ctx->n0 / 2};
+  return timed(ctx, 4, i, [&] { return launch_ypass<T, true>(ctx->n1, ctx->n2, yi, ctx->stream); });
+}
+
+struct SolveOut {
+  int iters = 0, done = 0;
+  Ctl ctl{};
+};
+
+// Fixed-point loop on the device. Strain buffers: iteration i reads
+// in(i) = (i == 0 ? ec : w[(i - 1) % 2]) and writes out(i) = w[i % 2].
+// Returns the iteration index that converged in out.iters (count).
+template <typename T, int MODE>
+fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0 c0, FinArgs& fin,
+                         const double* E_start, const double* dE, const void* lam0, const void* epsp,
+                         const void* rho, const void* sig_t, SolveOut& out) {
+  Ctl h{};
+  for (int k = 0; k < 6; ++k) h.E[k] = E_start[k];
+  *ctx->ctl_h = h;
+  HIPCHK(hipMemcpyAsync(ctx->ctl, ctx->ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+  const int w[2] = {(ctx->ec + 1) % 3, (ctx->ec + 2) % 3};
+  int launched = 0;
+  int chunk = std::max(4, ctx->last_iters + 2);
+  while (launched < o.max_iter) {
+    const int upto = std::min(o.max_iter, launched + chunk);
+    for (int i = launched; i < upto; ++i) {
+      const int in = i == 0 ? ctx->ec : w[(i - 1) % 2];
+      const int ob = w[i % 2];
+      const void* lam = i == 0 ? lam0 : ctx->b.sig[ctx->sw];
+      HIPCHK((enqueue_iteration<T, MODE>(ctx, i, in, ob, lam, ctx->b.sig[ctx->sw], epsp, rho, sig_t, m,
+                                          c0, fin, dE)));
+    }
+    launched = upto;
+    HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->prof) HIPCHK(harvest(ctx, ctx->ctl_h->iters, ctx->ctl_h->done != 0));
+    if (ctx->ctl_h->done) break;
+    chunk = 8;
+  }
+  out.ctl = *ctx->ctl_h;
+  out.iters = out.ctl.iters;
+  out.done = out.ctl.done;
+  const int k = out.iters - 1;
+  // buffer holding the strain of the latest completed iteration
+  if (out.done == 1) ctx->e_last = k == 0 ? ctx->ec : w[(k - 1) % 2];
+  else ctx->e_last = w[k % 2];
+  return FFTEVP_OK;
+}
+
+FinArgs make_fin(fftevp_ctx* ctx, const fftevp_opts& o, C0 c0) {
+  FinArgs f{};
+  f.partial = ctx->partial;
+  f.nblocks = ctx->local_nb;
+  f.nvox = (double)ctx->V;
+  f.tol = o.tol;
+  for (int k = 0; k < 6; ++k) f.strain_ctrl[k] = ctx->load.strain_ctrl[k] ? 1 : 0;
+  to_mandel(ctx->load.Sigma, f.sig_star);
+  c0ss_inverse(c0, f.strain_ctrl, f.css);
+  f.ctl = ctx->ctl;
+  return f;
+}
+
+fftevp_opts resolve_opts(const fftevp_ctx* ctx, const fftevp_opts* in) {
+  fftevp_opts o{};
+  if (in) o = *in;
+  if (!(o.tol > 0.0)) o.tol = 1e-6;
+  if (o.max_iter <= 0) o.max_iter = 1000;
+  if (o.newton_max <= 0) o.newton_max = 50;
+  return o;
+}
+
+template <typename T>
+fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* rep) {
+  const C0 c0 = reference_medium(ctx, &o);
+  const double dt = ctx->load.dt;
+  const Mat m = make_mat(ctx, c0, dt, sizeof(T) == 8 ? 1e-12 : 1e-5, o.newton_max);
+  FinArgs fin = make_fin(ctx, o, c0);
+  double Edot[6], E1[6], dE[6];
+  to_mandel(ctx->load.Edot, Edot);
+  for (int k = 0; k < 6; ++k) {
+    E1[k] = ctx->E[k] + (ctx->load.strain_ctrl[k] ? Edot[k] * dt : 0.0);
+    dE[k] = E1[k] - ctx->E[k];
+  }
+  SolveOut so;
+  fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, E1, dE, ctx->b.sig[ctx->sc],
+                                                ctx->b.epsp, ctx->b.rho, nullptr, so);
+  if (st != FFTEVP_OK) return st;
+  ctx->last_iters = so.iters;
+  fftevp_status ret = FFTEVP_OK;
+  double rho_mean = 0.0;
+  if (so.done == 2) {
+    ret = FFTEVP_ENONFINITE;
+    ctx->err = "non-finite residual or mean stress";
+  } else if (so.done != 1) {
+    ret = FFTEVP_NOT_CONVERGED;
+    ctx->err = "max_iter reached";
+  } else {
+    // commit: strain, stress, macroscopic strain, then the state update
+    const int k = so.iters - 1;
+    if (k == 0) {
+      HIPCHK(launch_shift_dc<T>((cx<T>*)ctx->b.emain[ctx->ec], ctx->planes, ctx->n0 / 2, dE, ctx->stream));
+    } else {
+      ctx->ec = ctx->e_last;
+    }
+    ctx->e_last = ctx->ec;
+    std::swap(ctx->sc, ctx->sw);
+    for (int q = 0; q < 6; ++q) ctx->E[q] = so.ctl.E[q];
+    StateArgs<T> sa{};
+    sa.sig = (const T*)ctx->b.sig[ctx->sc];
+    sa.quat = (const T*)ctx->b.quat;
+    sa.epsp = (T*)ctx->b.epsp;
+    sa.rho = (T*)ctx->b.rho;
+    sa.partial = ctx->partial;
+    sa.nvox = ctx->V;
+    sa.dt = dt;
+    sa.gdot0 = ctx->flow.gdot0;
+    sa.k1 = ctx->flow.k1;
+    sa.k2 = ctx->flow.k2;
+    sa.m = m;
+    HIPCHK(timed(ctx, 5, -1, [&] { return launch_state<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->prof) HIPCHK(harvest(ctx, 0, false));
+    rho_mean = ctx->red2_h[0] / (double)ctx->V;
+    ctx->t += dt;
+    ctx->inc += 1.0;
+    if (so.ctl.nfail > 0) {
+      ret = FFTEVP_ELOCAL;
+      ctx->err = "some voxel Newton solves reached newton_max";
+    }
+  }
+  if (rep) {
+    rep->iters = so.iters;
+    rep->newton_max_seen = (int)so.ctl.nmax;
+    rep->newton_failed = (int)so.ctl.nfail;
+    rep->err_c = so.ctl.err_c;
+    rep->err_bc = so.ctl.err_bc;
+    to_plain(so.ctl.Sigma, rep->Sigma);
+    to_plain(so.ctl.E, rep->E);
+    rep->rho_mean = rho_mean;
+  }
+  return ret;
+}
+
+size_t snap_layout(const fftevp_ctx* c, size_t off[6]) {
+  const size_t ts = c->tsize, V = c->V;
+  size_t o = kHeader * sizeof(double);
+  off[0] = o;  // epsp
+  o += 6 * V * ts;
+  off[1] = o;  // rho
+  o += V * ts;
+  off[2] = o;  // sigma
+  o += 6 * V * ts;
+  off[3] = o;  // strain spectra
+  o += 6 * V * ts;
+  off[4] = o;  // strain Nyquist planes
+  o += 6 * c->planes * ts;
+  o = (o + 255) & ~(size_t)255;
+  off[5] = o;
+  return o;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* fftevp_status_string(fftevp_status s) {
+  switch (s) {
+    case FFTEVP_OK: return "ok";
+    case FFTEVP_NOT_CONVERGED: return "not converged";
+    case FFTEVP_EINVAL: return "invalid argument";
+    case FFTEVP_ENOMEM: return "out of device memory";
+    case FFTEVP_EHIP: return "HIP runtime error";
+    case FFTEVP_ENONFINITE: return "non-finite result";
+    case FFTEVP_ELOCAL: return "local Newton solve did not converge";
+    case FFTEVP_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* fftevp_last_error(const fftevp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fftevp_status fftevp_create(int n0, int n1, int n2, fftevp_precision precision, void* hip_stream,
+                            fftevp_ctx** out) {
+  if (!out) return FFTEVP_EINVAL;
+  *out = nullptr;
+  if (!pow2_in_range(n0) || !pow2_in_range(n1) || !pow2_in_range(n2)) return FFTEVP_EINVAL;
+  if (precision != FFTEVP_FP64 && precision != FFTEVP_MIXED) return FFTEVP_EINVAL;
+  fftevp_ctx* ctx = new fftevp_ctx();
+  ctx->n0 = n0;
+  ctx->n1 = n1;
+  ctx->n2 = n2;
+  ctx->planes = (size_t)n1 * n2;
+  ctx->V = ctx->planes * n0;
+  ctx->prec = precision;
+  ctx->tsize = precision == FFTEVP_FP64 ? 8 : 4;
+  ctx->stream = (hipStream_t)hip_stream;
+  fftevp_status s = precision == FFTEVP_FP64 ? alloc_all<double>(ctx) : alloc_all<float>(ctx);
+  if (s != FFTEVP_OK) {
+    free_all(ctx);
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_destroy(fftevp_ctx* ctx) {
+  if (!ctx) return FFTEVP_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_set_material(fftevp_ctx* ctx, const fftevp_cubic* c, const fftevp_flow* f) {
+  if (!ctx || !c || !f) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  const double v[11] = {c->C11, c->C12, c->C44, f->tau0, f->k1, f->k2, f->n, f->gdot0, f->alpha, f->mu, f->b};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(ctx, FFTEVP_EINVAL, "non-finite material parameter");
+  if (!(c->C11 > std::fabs(c->C12) && c->C11 + 2.0 * c->C12 > 0.0 && c->C44 > 0.0))
+    return fail(ctx, FFTEVP_EINVAL, "cubic constants not positive definite");
+  if (!(f->n >= 1.0 && f->gdot0 >= 0.0 && f->tau0 > 0.0 && f->alpha >= 0.0 && f->mu >= 0.0 && f->b >= 0.0 &&
+        f->k1 >= 0.0 && f->k2 >= 0.0))
+    return fail(ctx, FFTEVP_EINVAL, "flow parameters out of range");
+  ctx->cubic = *c;
+  ctx->flow = *f;
+  ctx->have_mat = true;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat, const double* rho) {
+  if (!ctx || !quat || !rho) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  const size_t V = ctx->V;
+  hipError_t e = ctx->prec == FFTEVP_FP64
+                     ? launch_ingest<double>(quat, rho, (double*)ctx->b.quat, (double*)ctx->b.rho, V,
+                                             ctx->partial, ctx->red_nb, ctx->red2, ctx->stream)
+                     : launch_ingest<float>(quat, rho, (float*)ctx->b.quat, (float*)ctx->b.rho, V, ctx->partial,
+                                            ctx->red_nb, ctx->red2, ctx->stream);
+  HIPCHK(e);
+  HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->red2_h[0] > 0 || ctx->red2_h[1] > 0) {
+    ctx->have_micro = false;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%.0f quaternions not unit within 1e-6, %.0f densities not finite and > 0",
+             ctx->red2_h[0], ctx->red2_h[1]);
+    return fail(ctx, FFTEVP_EINVAL, buf);
+  }
+  // fresh mechanical state
+  const size_t ts = ctx->tsize;
+  HIPCHK(hipMemsetAsync(ctx->b.epsp, 0, 6 * V * ts, ctx->stream));
+  for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(ctx->b.sig[i], 0, 6 * V * ts, ctx->stream));
+  for (int i = 0; i < 3; ++i) {
+    HIPCHK(hipMemsetAsync(ctx->b.emain[i], 0, 6 * V * ts, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->b.enyq[i], 0, 6 * ctx->planes * ts, ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < 6; ++k) ctx->E[k] = 0.0;
+  ctx->t = 0.0;
+  ctx->inc = 0.0;
+  ctx->ec = ctx->e_last = 0;
+  ctx->sc = 0;
+  ctx->sw = 1;
+  ctx->last_iters = 0;
+  ctx->have_micro = true;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_set_loading(fftevp_ctx* ctx, const fftevp_loading* l) {
+  if (!ctx || !l) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  int nsc = 0;
+  for (int k = 0; k < 6; ++k) {
+    if (!std::isfinite(l->Edot[k]) || !std::isfinite(l->Sigma[k]))
+      return fail(ctx, FFTEVP_EINVAL, "non-finite loading");
+    if (l->strain_ctrl[k] != 0 && l->strain_ctrl[k] != 1)
+      return fail(ctx, FFTEVP_EINVAL, "strain_ctrl entries must be 0 or 1");
+    nsc += l->strain_ctrl[k];
+  }
+  if (nsc == 0) return fail(ctx, FFTEVP_EINVAL, "at least one component must be strain controlled");
+  if (!(l->dt > 0.0) || !std::isfinite(l->dt)) return fail(ctx, FFTEVP_EINVAL, "dt must be > 0");
+  ctx->load = *l;
+  ctx->have_load = true;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_report* out) {
+  if (!ctx) return FFTEVP_EINVAL;
+  if (!ctx->have_mat || !ctx->have_micro || !ctx->have_load)
+    return fail(ctx, FFTEVP_ESTATE, "set_material, set_microstructure and set_loading must come first");
+  if (opts && (!(opts->tol >= 0.0) || opts->c0_mu < 0.0 || (opts->c0_mu > 0.0 && !(opts->c0_lambda + 2.0 * opts->c0_mu / 3.0 > 0.0))))
+    return fail(ctx, FFTEVP_EINVAL, "bad options");
+  const fftevp_opts o = resolve_opts(ctx, opts);
+  return ctx->prec == FFTEVP_FP64 ? step_impl<double>(ctx, o, out) : step_impl<float>(ctx, o, out);
+}
+
+fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
+  if (!ctx || !dst) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  const size_t V = ctx->V;
+  const bool dbl = ctx->prec == FFTEVP_FP64;
+  auto exp = [&](const void* src, int ncomp, int mandel) {
+    return dbl ? launch_export<double>((const double*)src, dst, V, ncomp, mandel, ctx->stream)
+               : launch_export<float>((const float*)src, dst, V, ncomp, mandel, ctx->stream);
+  };
+  auto strain = [&](int buf) {
+    Mat m{};
+    if (dbl) {
+      LocalArgs<double> la{};
+      la.e_main = (const cx<double>*)ctx->b.emain[buf];
+      la.e_nyq = (const double*)ctx->b.enyq[buf];
+      la.tw = (const cx<double>*)ctx->b.tw[0];
+      la.out = dst;
+      la.n1 = ctx->n1;
+      la.n2 = ctx->n2;
+      la.m = m;
+      return launch_local<double, MODE_EXPORT>(ctx->n0, la, ctx->stream);
+    }
+    LocalArgs<float> la{};
+    la.e_main = (const cx<float>*)ctx->b.emain[buf];
+    la.e_nyq = (const float*)ctx->b.enyq[buf];
+    la.tw = (const cx<float>*)ctx->b.tw[0];
+    la.out = dst;
+    la.n1 = ctx->n1;
+    la.n2 = ctx->n2;
+    la.m = m;
+    return launch_local<float, MODE_EXPORT>(ctx->n0, la, ctx->stream);
+  };
+  hipError_t e;
+  switch (field) {
+    case FFTEVP_FIELD_SIGMA: e = exp(ctx->b.sig[ctx->sc], 6, 1); break;
+    case FFTEVP_FIELD_STRAIN: e = strain(ctx->ec); break;
+    case FFTEVP_FIELD_EPS_P: e = exp(ctx->b.epsp, 6, 1); break;
+    case FFTEVP_FIELD_RHO: e = exp(ctx->b.rho, 1, 0); break;
+    case FFTEVP_FIELD_SIGMA_ITER: e = exp(ctx->b.sig[ctx->sw], 6, 1); break;
+    case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->e_last); break;
+    default: return fail(ctx, FFTEVP_EINVAL, "unknown field");
+  }
+  HIPCHK(e);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FFTEVP_OK;
+}
+
+size_t fftevp_state_bytes(const fftevp_ctx* ctx) {
+  if (!ctx) return 0;
+  size_t off[6];
+  return snap_layout(ctx, off);
+}
+
+fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
+  if (!ctx || !dst) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  size_t off[6];
+  snap_layout(ctx, off);
+  const size_t ts = ctx->tsize, V = ctx->V;
+  double hdr[kHeader] = {0};
+  hdr[0] = kSnapMagic;
+  hdr[1] = (double)ctx->prec;
+  hdr[2] = ctx->n0;
+  hdr[3] = ctx->n1;
+  hdr[4] = ctx->n2;
+  for (int k = 0; k < 6; ++k) hdr[5 + k] = ctx->E[k];
+  hdr[11] = ctx->t;
+  hdr[12] = ctx->inc;
+  hdr[13] = ctx->last_iters;
+  char* d = (char*)dst;
+  HIPCHK(hipMemcpyAsync(d, hdr, sizeof hdr, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d + off[0], ctx->b.epsp, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d + off[1], ctx->b.rho, V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d + off[2], ctx->b.sig[ctx->sc], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d + off[3], ctx->b.emain[ctx->ec], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d + off[4], ctx->b.enyq[ctx->ec], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
+  if (!ctx || !src) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  size_t off[6];
+  snap_layout(ctx, off);
+  const size_t ts = ctx->tsize, V = ctx->V;
+  double hdr[kHeader];
+  const char* s = (const char*)src;
+  HIPCHK(hipMemcpyAsync(hdr, s, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
+      hdr[4] != ctx->n2)
+    return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
+  HIPCHK(hipMemcpyAsync(ctx->b.epsp, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.rho, s + off[1], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.sig[ctx->sc], s + off[2], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.emain[ctx->ec], s + off[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.enyq[ctx->ec], s + off[4], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < 6; ++k) ctx->E[k] = hdr[5 + k];
+  ctx->t = hdr[11];
+  ctx->inc = hdr[12];
+  ctx->last_iters = (int)hdr[13];
+  ctx->e_last = ctx->ec;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int enable) {
+  if (!ctx) return FFTEVP_EINVAL;
+  ctx->prof = enable != 0;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_get_profile(fftevp_ctx* ctx, double* ms, long long* launches, int reset) {
+  if (!ctx) return FFTEVP_EINVAL;
+  for (int k = 0; k < FFTEVP_NPROF; ++k) {
+    if (ms) ms[k] = ctx->prof_ms[k];
+    if (launches) launches[k] = ctx->prof_n[k];
+    if (reset) {
+      ctx->prof_ms[k] = 0.0;
+      ctx->prof_n[k] = 0;
+    }
+  }
+  return FFTEVP_OK;
+}
+
+size_t fftevp_adjoint_bytes(const fftevp_ctx* ctx) {
+  if (!ctx) return 0;
+  return 7 * ctx->V * ctx->tsize;
+}
+
+fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts*, const void*, const void*,
+                                       const double*, void*, double*) {
+  return fail(ctx, FFTEVP_ESTATE, "adjoint not available");
+}
+
+}  // extern "C"

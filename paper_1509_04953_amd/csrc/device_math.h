@@ -1,0 +1,287 @@
+// Per-voxel crystal mechanics for the local solve (device side).
+//
+// Symmetric tensors are Mandel 6-vectors [11, 22, 33, r2*23, r2*13, r2*12]
+// (r2 = sqrt 2), so double contraction is a dot product. The local problem
+// is solved in the crystal frame of the voxel: there the cubic compliance has
+// three distinct entries, the isotropic reference medium is unchanged, and
+// the Schmid tensors of the 12 FCC {111}<110> systems are fixed sign
+// patterns, so each resolved shear costs a few additions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+namespace fftevp {
+
+// Crystal-frame Schmid vectors: m_a[k] = kSign[a][k] * (1/sqrt6 for the
+// normal slots, 1/sqrt12 for the shear slots). Systems: plane normals
+// (111), (-111), (1-11), (11-1); per plane the three <110> directions in the
+// plane, i.e. m = sym(d x n) with |n| = |d| = 1 and n.d = 0. Shear is signed,
+// so each system appears once.
+constexpr int kSign[12][6] = {
+    {0, 1, -1, 0, -1, 1},  {1, 0, -1, -1, 0, 1},  {1, -1, 0, -1, 1, 0},
+    {0, 1, -1, 0, 1, -1},  {-1, 0, 1, 1, 0, 1},   {-1, 1, 0, 1, 1, 0},
+    {0, -1, 1, 0, 1, 1},   {1, 0, -1, 1, 0, -1},  {1, -1, 0, 1, 1, 0},
+    {0, 1, -1, 0, 1, 1},   {1, 0, -1, 1, 0, 1},   {1, -1, 0, 1, -1, 0},
+};
+
+constexpr double kR2 = 1.41421356237309504880;
+constexpr double kIR2 = 0.70710678118654752440;
+constexpr double kUN = 0.40824829046386301637;   // 1/sqrt(6)
+constexpr double kUS = 0.28867513459481288225;   // 1/sqrt(12)
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+__host__ __device__ constexpr int tri(int i, int j) {  // packed lower triangle
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+// Material constants of one solve, all FP64 on the host side.
+struct Mat {
+  double a_d, a_o, a_s;   // A = C0^-1 + S in the crystal frame (cubic form)
+  double s_d, s_o, s_s;   // S in the crystal frame (cubic form)
+  double c0l, c0m;        // reference medium: lambda0, mu0
+  double ci_d, ci_o, ci_s;  // C0^-1 (Mandel: normal diag, normal off, shear)
+  double c1;              // dt * gdot0
+  double n;               // rate exponent
+  int n_int;              // n if n is a positive integer, else 0
+  int newton_max;
+  double ntol;            // Newton step tolerance (relative)
+  double tau0, taylor;    // tauc = tau0 + taylor * sqrt(rho), taylor = alpha mu b
+  double inv_n0;          // 1 / n0
+};
+
+template <typename T>
+__device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T (&R)[9]) {
+  R[0] = T(1) - T(2) * (y * y + z * z);
+  R[1] = T(2) * (x * y - w * z);
+  R[2] = T(2) * (x * z + w * y);
+  R[3] = T(2) * (x * y + w * z);
+  R[4] = T(1) - T(2) * (x * x + z * z);
+  R[5] = T(2) * (y * z - w * x);
+  R[6] = T(2) * (x * z - w * y);
+  R[7] = T(2) * (y * z + w * x);
+  R[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+template <typename T>
+__device__ __forceinline__ void to_sym3(const T (&a)[6], T (&A)[9]) {
+  const T h = T(kIR2);
+  A[0] = a[0];
+  A[4] = a[1];
+  A[8] = a[2];
+  A[5] = A[7] = h * a[3];
+  A[2] = A[6] = h * a[4];
+  A[1] = A[3] = h * a[5];
+}
+
+// crystal components of a sample-frame tensor: R^T A R
+template <typename T>
+__device__ __forceinline__ void to_crystal(const T (&R)[9], const T (&a)[6], T (&o)[6]) {
+  T A[9], B[9];
+  to_sym3(a, A);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      B[3 * i + j] = A[3 * i] * R[j] + A[3 * i + 1] * R[3 + j] + A[3 * i + 2] * R[6 + j];
+  auto c = [&](int i, int j) { return R[i] * B[j] + R[3 + i] * B[3 + j] + R[6 + i] * B[6 + j]; };
+  const T r2 = T(kR2);
+  o[0] = c(0, 0);
+  o[1] = c(1, 1);
+  o[2] = c(2, 2);
+  o[3] = r2 * c(1, 2);
+  o[4] = r2 * c(0, 2);
+  o[5] = r2 * c(0, 1);
+}
+
+// sample components of a crystal-frame tensor: R A R^T
+template <typename T>
+__device__ __forceinline__ void to_sample(const T (&R)[9], const T (&a)[6], T (&o)[6]) {
+  T A[9], B[9];
+  to_sym3(a, A);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      B[3 * i + j] = A[3 * i] * R[3 * j] + A[3 * i + 1] * R[3 * j + 1] + A[3 * i + 2] * R[3 * j + 2];
+  auto c = [&](int i, int j) {
+    return R[3 * i] * B[j] + R[3 * i + 1] * B[3 + j] + R[3 * i + 2] * B[6 + j];
+  };
+  const T r2 = T(kR2);
+  o[0] = c(0, 0);
+  o[1] = c(1, 1);
+  o[2] = c(2, 2);
+  o[3] = r2 * c(1, 2);
+  o[4] = r2 * c(0, 2);
+  o[5] = r2 * c(0, 1);
+}
+
+template <int C, typename T>
+__device__ __forceinline__ void acc_sign(T& acc, T v) {
+  if constexpr (C > 0) acc += v;
+  else if constexpr (C < 0) acc -= v;
+}
+
+// resolved shear of system A (crystal-frame Mandel stress)
+template <int A, typename T>
+__device__ __forceinline__ T resolved(const T (&s)[6]) {
+  T tn = T(0), ts = T(0);
+  acc_sign<kSign[A][0]>(tn, s[0]);
+  acc_sign<kSign[A][1]>(tn, s[1]);
+  acc_sign<kSign[A][2]>(tn, s[2]);
+  acc_sign<kSign[A][3]>(ts, s[3]);
+  acc_sign<kSign[A][4]>(ts, s[4]);
+  acc_sign<kSign[A][5]>(ts, s[5]);
+  return T(kUN) * tn + T(kUS) * ts;
+}
+
+// |x|^(n-1) for x >= 0; integral n by repeated squaring
+template <typename T>
+__device__ __forceinline__ T pow_nm1(T ax, T n, int n_int) {
+  if (n_int > 0) {
+    T r = T(1), b = ax;
+    int e = n_int - 1;
+    while (e) {
+      if (e & 1) r *= b;
+      b *= b;
+      e >>= 1;
+    }
+    return r;
+  }
+  return ax > T(0) ? exp((n - T(1)) * log(ax)) : (n == T(1) ? T(1) : T(0));
+}
+
+// Flow at a crystal-frame stress s:
+//   w[a]  = |x_a|^(n-1),  x_a = tau_a / tauc
+//   g[k]  = sum_a sign(x_a)|x_a|^n kSign[a][k]   (epsdot_p = gdot0 * u_k g[k])
+//   visc  = sum_a |x_a|^(n+1)
+//   asum  = sum_a |x_a|^n
+template <typename T>
+__device__ __forceinline__ void flow_eval(const T (&s)[6], T itauc, T n, int n_int, T (&w)[12],
+                                          T (&g)[6], T& visc, T& asum) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = T(0);
+  visc = T(0);
+  asum = T(0);
+  static_for<0, 12>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    const T x = resolved<A>(s) * itauc;
+    const T ax = fabs(x);
+    const T wa = pow_nm1(ax, n, n_int);
+    const T p = wa * ax;
+    w[A] = wa;
+    visc += p * ax;
+    asum += p;
+    const T sp = x < T(0) ? -p : p;
+    static_for<0, 6>([&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      acc_sign<kSign[A][K]>(g[K], sp);
+    });
+  });
+}
+
+// cubic-form 6x6 (Mandel) times vector: normal block (d, o), shear diag s
+template <typename T>
+__device__ __forceinline__ void cubic_mul(T d, T o, T sh, const T (&v)[6], T (&out)[6]) {
+  out[0] = d * v[0] + o * (v[1] + v[2]);
+  out[1] = d * v[1] + o * (v[0] + v[2]);
+  out[2] = d * v[2] + o * (v[0] + v[1]);
+  out[3] = sh * v[3];
+  out[4] = sh * v[4];
+  out[5] = sh * v[5];
+}
+
+// residual and potential of the local problem in the crystal frame:
+//   r   = A s - b + c1 * m(g)
+//   phi = 1/2 s.A s - b.s + c1 tauc/(n+1) visc
+template <typename T>
+__device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], const T (&b)[6],
+                                               T tauc, T itauc, T (&w)[12], T (&r)[6], T& phi) {
+  T g[6], visc, asum;
+  flow_eval(s, itauc, T(M.n), M.n_int, w, g, visc, asum);
+  T As[6];
+  cubic_mul(T(M.a_d), T(M.a_o), T(M.a_s), s, As);
+  const T c1 = T(M.c1);
+  T q = T(0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const T u = k < 3 ? T(kUN) : T(kUS);
+    r[k] = As[k] - b[k] + c1 * u * g[k];
+    q += s[k] * (T(0.5) * As[k] - b[k]);
+  }
+  phi = q + c1 * tauc / (T(M.n) + T(1)) * visc;
+}
+
+// J = A + cj * sum_a w_a m_a m_a^T  (packed lower triangle, 21 entries)
+template <typename T>
+__device__ __forceinline__ void local_jacobian(const Mat& M, const T (&w)[12], T cj, T (&J)[21]) {
+  T H[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) H[k] = T(0);
+  static_for<0, 12>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    static_for<0, 6>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      static_for<0, I + 1>([&](auto jc) {
+        constexpr int J2 = decltype(jc)::value;
+        constexpr int c = kSign[A][I] * kSign[A][J2];
+        acc_sign<c>(H[tri(I, J2)], w[A]);
+      });
+    });
+  });
+  const T nn = cj * T(1.0 / 6.0), ns = cj * T(kUN * kUS), ss = cj * T(1.0 / 12.0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const T f = (i < 3 && j < 3) ? nn : ((i >= 3 && j >= 3) ? ss : ns);
+      T a = T(0);
+      if (i < 3 && j < 3) a = (i == j) ? T(M.a_d) : T(M.a_o);
+      else if (i == j) a = T(M.a_s);
+      J[tri(i, j)] = a + f * H[tri(i, j)];
+    }
+}
+
+// Solve J x = rhs for SPD J (packed lower triangle) by J = L D L^T with unit
+// lower L. P holds L scaled by D column-wise (P_ij = L_ij d_j), id = 1/d.
+template <typename T>
+__device__ __forceinline__ void ldl_solve(const T (&J)[21], const T (&rhs)[6], T (&x)[6]) {
+  T P[21], id[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T d = J[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= P[tri(j, k)] * P[tri(j, k)] * id[k];
+    id[j] = T(1) / d;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      T v = J[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= P[tri(i, k)] * P[tri(j, k)] * id[k];
+      P[tri(i, j)] = v;
+    }
+  }
+  T y[6];  // L y = rhs
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T v = rhs[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= P[tri(i, k)] * id[k] * y[k];
+    y[i] = v;
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {  // L^T x = D^-1 y
+    T v = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) v -= P[tri(k, i)] * x[k];
+    x[i] = v * id[i];
+  }
+}
+
+}  // namespace fftevp

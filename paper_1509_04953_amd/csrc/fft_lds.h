@@ -1,0 +1,152 @@
+// Batched power-of-two complex FFTs on lines held in LDS (gfx950).
+//
+// Each stage is a Stockham autosort radix-R pass (natural order in and out):
+// every thread loads its butterflies' inputs into registers, the block
+// synchronises, then the thread applies twiddles, the in-register radix-R
+// DFT and writes the outputs back to the same LDS buffer. Reading everything
+// before any write lets one buffer serve as both source and destination.
+// Twiddles come from a table w[m] = exp(-2 pi i m / N), m in [0, N), built on
+// the host in extended precision. Forward transforms are unnormalised; the
+// inverse uses conjugate twiddles and is unnormalised too.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fftevp {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+  if constexpr (INV) return {-a.y, a.x};
+  else return {a.y, -a.x};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+  cx<T> t2 = v[1] + v[3], t3 = rot90<T, INV>(v[1] - v[3]);
+  v[0] = t0 + t2;
+  v[2] = t0 - t2;
+  v[1] = t1 + t3;
+  v[3] = t1 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  const T h = T(0.70710678118654752440);
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<T, INV>(e);
+  dft4<T, INV>(o);
+  // o[k] *= exp(-+ i pi k / 4)
+  cx<T> o1, o3;
+  if constexpr (INV) {
+    o1 = {h * (o[1].x - o[1].y), h * (o[1].x + o[1].y)};
+    o3 = {-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y)};
+  } else {
+    o1 = {h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+    o3 = {h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+  }
+  cx<T> o2 = rot90<T, INV>(o[2]);
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + o1;
+  v[5] = e[1] - o1;
+  v[2] = e[2] + o2;
+  v[6] = e[2] - o2;
+  v[3] = e[3] + o3;
+  v[7] = e[3] - o3;
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+  if constexpr (R == 2) dft2<T, INV>(v);
+  else if constexpr (R == 4) dft4<T, INV>(v);
+  else dft8<T, INV>(v);
+}
+
+// One Stockham stage over LINES lines of length N (line stride LS, unit
+// element stride) with NT cooperating threads.
+template <typename T, int N, int R, int NS, bool INV, int LINES, int LS, int NT>
+__device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
+                                               const cx<T>* __restrict__ tw) {
+  constexpr int BF = N / R;
+  constexpr int TOTAL = LINES * BF;
+  constexpr int PER = (TOTAL + NT - 1) / NT;
+  cx<T> v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = tid + b * NT;
+    if ((TOTAL % NT) == 0 || idx < TOTAL) {
+      const int line = idx / BF, j = idx % BF;
+      const cx<T>* src = buf + line * LS + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[r * BF];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = tid + b * NT;
+    if ((TOTAL % NT) == 0 || idx < TOTAL) {
+      const int line = idx / BF, j = idx % BF;
+      const int k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> w = tw[k * r * (N / (NS * R))];
+          v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+        }
+      }
+      dftR<T, R, INV>(v[b]);
+      cx<T>* dst = buf + line * LS + (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int NS, bool INV, int LINES, int LS, int NT>
+__device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw) {
+  if constexpr (NS < N) {
+    // radix plan: 8s first, then a final 4 or 2 (16 -> 4x4, 128 -> 8x4x4)
+    constexpr int REM = N / NS;
+    constexpr int R = (REM % 8 == 0 && REM != 16) ? 8 : (REM % 4 == 0 ? 4 : 2);
+    stockham_stage<T, N, R, NS, INV, LINES, LS, NT>(buf, tw);
+    fft_rest<T, N, NS * R, INV, LINES, LS, NT>(buf, tw);
+  }
+}
+
+// In-place FFT of LINES lines of length N held in LDS (line stride LS).
+// Must be called by all NT threads of the block; ends with a barrier.
+template <typename T, int N, bool INV, int LINES, int LS, int NT>
+__device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* __restrict__ tw) {
+  fft_rest<T, N, 1, INV, LINES, LS, NT>(buf, tw);
+}
+
+}  // namespace fftevp

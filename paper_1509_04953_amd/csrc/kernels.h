@@ -1,0 +1,115 @@
+// Launch interface between the C-ABI layer and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "device_math.h"
+#include "fft_lds.h"
+
+namespace fftevp {
+
+enum { MODE_NEWTON = 0, MODE_TANGENT = 1, MODE_EXPORT = 2 };
+
+// per-block partial sums of the local kernel:
+// [0] sum |e - eps|^2, [1..6] sum sigma, [7] sum sigma:e, [8] Newton failures,
+// [9] max Newton iterations (reduced by max)
+constexpr int NPART = 10;
+
+// Device-resident control block of one increment.
+struct Ctl {
+  double E[6];      // macroscopic strain (Mandel) used by the next spectral update
+  double Sigma[6];  // mean stress of the latest iterate (Mandel)
+  double err_c, err_bc, se, nfail, nmax;
+  int done;         // 0 running, 1 converged, 2 non-finite
+  int iters;        // completed local solves
+};
+
+template <typename T>
+struct LocalArgs {
+  const cx<T>* e_main;  // x-half-spectrum of e, [6][n2][n1][n0/2]
+  const T* e_nyq;       // x-Nyquist plane of e, [6][n2][n1]
+  cx<T>* t_main;        // out: x-half-spectrum of tau
+  T* e_nyq_next;        // out: x-Nyquist plane of the next e
+  const T* lam;         // multiplier (previous stress), [6][V] Mandel
+  T* sig;               // out: stress, [6][V] Mandel
+  const T* epsp;        // plastic strain (tangent mode: eigenstrain), [6][V]
+  const T* rho;         // density, [V]
+  const T* quat;        // orientation, [4][V]
+  const T* sig_t;       // tangent mode: stress the tangent is taken at
+  double* partial;      // [blocks][NPART]
+  const Ctl* ctl;
+  const cx<T>* tw;      // twiddles for n0
+  double* out;          // export mode: plain-component strain, [6][V] FP64
+  double dE[6];
+  int add_dE;
+  int n1, n2;
+  Mat m;
+};
+
+template <typename T>
+struct YArgs {
+  const cx<T>* src;
+  cx<T>* dst;
+  const cx<T>* tw;
+  const Ctl* ctl;
+  int h;  // n0 / 2
+};
+
+template <typename T>
+struct ZArgs {
+  cx<T>* buf;
+  const cx<T>* tw;
+  const Ctl* ctl;
+  int h, n1;
+  double inv_n0, inv_n1, inv_n2, inv_ntot;
+  double c0l, c0m, ci_d, ci_o, ci_s;
+};
+
+struct FinArgs {
+  const double* partial;
+  int nblocks;
+  double nvox, tol;
+  int strain_ctrl[6];
+  double sig_star[6];  // Mandel
+  double css[36];      // [(C0)_ss]^-1 embedded in 6x6 (Mandel), zero elsewhere
+  Ctl* ctl;
+};
+
+template <typename T>
+struct StateArgs {
+  const T* sig;
+  const T* quat;
+  T* epsp;
+  T* rho;
+  double* partial;  // [blocks][2]: sum rho_new, sum sum_a |gdot_a|
+  size_t nvox;
+  double dt, gdot0, k1, k2;
+  Mat m;
+};
+
+struct Shift6 {
+  double v[6];
+};
+
+template <typename T, int MODE>
+hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s);
+template <typename T>
+int local_blocks(int n0, int n1, int n2);
+template <typename T, bool INV>
+hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s);
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+template <typename T>
+hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
+template <typename T>
+hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
+                         int nblocks, double* out2, hipStream_t s);
+template <typename T>
+hipError_t launch_export(const T* src, double* dst, size_t V, int ncomp, int mandel, hipStream_t s);
+template <typename T>
+hipError_t launch_shift_dc(cx<T>* main, size_t planes, int h, const double dE[6], hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
+
+}  // namespace fftevp

@@ -1,0 +1,716 @@
+// FFT-EVP fixed-point iteration kernels for gfx950.
+//
+// One iteration of the augmented-Lagrangian scheme (Sec. 2.1, Eq. 1-2) is
+// four passes over HBM plus a one-block reduction:
+//   k_local    per x-line: inverse real FFT along x of the compatible strain
+//              (LDS), local Newton solve per voxel (registers), polarisation
+//              tau = sigma - C0:eps, forward real FFT along x (LDS); FP64
+//              partial sums of the residual and the mean stress.
+//   k_finalize one block: deterministic reduction, stop test, mixed
+//              boundary-condition update of the macroscopic strain.
+//   k_ypass    forward FFT along y (tiles of x-frequencies, LDS).
+//   k_zgamma   forward FFT along z, Green operator per frequency, inverse
+//              FFT along z, for all six components at once (LDS).
+//   k_ypass    inverse FFT along y into the next strain buffer.
+// The x-Nyquist plane never needs y/z transforms: there the Green operator
+// is the constant C0^-1, so k_local writes the next strain's Nyquist plane
+// directly. Every kernel first reads the device stop flag and exits if the
+// iteration has converged, so the host can enqueue iterations ahead.
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "fft_lds.h"
+#include "kernels.h"
+
+namespace fftevp {
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block of 256 threads: reduce NP values (the last NMAX of them by max) and
+// write them to out[0..NP). Deterministic order.
+template <int NP, int NMAX>
+__device__ __forceinline__ void block_reduce(double (&v)[NP], double* __restrict__ out) {
+  __shared__ double red[4][NP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double r = (k >= NP - NMAX) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0) red[wv][k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < NP) {
+    const int k = threadIdx.x;
+    double r = red[0][k];
+    for (int w = 1; w < 4; ++w) r = (k >= NP - NMAX) ? fmax(r, red[w][k]) : r + red[w][k];
+    out[k] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// local kernel
+// ---------------------------------------------------------------------------
+template <typename T, int N0>
+struct LocalShape {
+  static constexpr int NT = 256;
+  static constexpr int LPB = N0 >= NT ? 1 : NT / N0;   // x-lines per block
+  static constexpr int VPT = N0 > NT ? N0 / NT : 1;    // voxels per thread
+  static constexpr int LS = N0 + 1;                    // LDS line stride
+  static constexpr int H = N0 / 2;
+};
+
+// Load the x-half-spectra of the six strain components of this block's lines
+// and pack them pairwise as Z = Xa + i Xb over the full length N0 (Hermitian
+// extension), ready for one inverse complex FFT per pair.
+template <typename T, int N0>
+__device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, const T* __restrict__ nyq,
+                                            size_t line0, size_t vox, size_t planes, cx<T>* sh) {
+  using S = LocalShape<T, N0>;
+  constexpr int PER_LINE = S::H + 1;
+  for (int idx = threadIdx.x; idx < 3 * S::LPB * PER_LINE; idx += S::NT) {
+    const int p = idx / (S::LPB * PER_LINE);
+    const int rem = idx - p * (S::LPB * PER_LINE);
+    const int l = rem / PER_LINE, k = rem - l * PER_LINE;
+    const size_t line = line0 + l;
+    cx<T> xa, xb;
+    if (k < S::H) {
+      xa = main[(size_t)(2 * p) * (vox / 2) + line * S::H + k];
+      xb = main[(size_t)(2 * p + 1) * (vox / 2) + line * S::H + k];
+      if (k == 0) {
+        xa.y = T(0);
+        xb.y = T(0);
+      }
+    } else {
+      xa = {nyq[(size_t)(2 * p) * planes + line], T(0)};
+      xb = {nyq[(size_t)(2 * p + 1) * planes + line], T(0)};
+    }
+    cx<T>* Z = sh + (p * S::LPB + l) * S::LS;
+    Z[k] = {xa.x - xb.y, xa.y + xb.x};
+    if (k > 0 && k < S::H) Z[N0 - k] = {xa.x + xb.y, xb.x - xa.y};
+  }
+}
+
+template <typename T, int N0, int MODE>
+__global__ __launch_bounds__(256) void k_local(LocalArgs<T> a) {
+  using S = LocalShape<T, N0>;
+  if (a.ctl && a.ctl->done) return;
+  __shared__ cx<T> sh[3 * S::LPB * S::LS];
+  const size_t planes = (size_t)a.n1 * a.n2;
+  const size_t vox = planes * N0;
+  const size_t line0 = (size_t)blockIdx.x * S::LPB;
+  const Mat& M = a.m;
+
+  load_packed<T, N0>(a.e_main, a.e_nyq, line0, vox, planes, sh);
+  __syncthreads();
+  fft_lines<T, N0, true, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
+
+  if constexpr (MODE == MODE_EXPORT) {
+    // write the real strain, plain components, FP64
+#pragma unroll
+    for (int v = 0; v < S::VPT; ++v) {
+      const int t = threadIdx.x + v * S::NT;
+      const int l = t / N0, x = t - (t / N0) * N0;
+      const size_t g = (line0 + l) * N0 + x;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
+        const double f0 = (2 * p >= 3) ? kIR2 : 1.0;
+        const double f1 = (2 * p + 1 >= 3) ? kIR2 : 1.0;
+        a.out[(size_t)(2 * p) * vox + g] = f0 * (double)z.x;
+        a.out[(size_t)(2 * p + 1) * vox + g] = f1 * (double)z.y;
+      }
+    }
+    return;
+  }
+
+  double part[NPART];
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) part[k] = 0.0;
+
+  const T ci_d = T(M.ci_d), ci_o = T(M.ci_o), ci_s = T(M.ci_s);
+  const T c0l = T(M.c0l), c0m2 = T(2.0 * M.c0m);
+
+#pragma unroll 1
+  for (int v = 0; v < S::VPT; ++v) {
+    const int t = threadIdx.x + v * S::NT;
+    const int l = t / N0, x = t - (t / N0) * N0;
+    const size_t g = (line0 + l) * N0 + x;
+    T e[6], lam[6], ep[6];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
+      e[2 * p] = z.x;
+      e[2 * p + 1] = z.y;
+    }
+    if (a.add_dE) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] += T(a.dE[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      lam[k] = a.lam[(size_t)k * vox + g];
+      ep[k] = a.epsp[(size_t)k * vox + g];
+    }
+    T R[9];
+    {
+      const T qw = a.quat[g], qx = a.quat[vox + g], qy = a.quat[2 * vox + g], qz = a.quat[3 * vox + g];
+      quat_rot(qw, qx, qy, qz, R);
+    }
+    const T tauc = T(M.tau0) + T(M.taylor) * sqrt(a.rho[g]);
+    const T itauc = T(1) / tauc;
+
+    // b = C0^-1 lam + e - epsp   (sample frame), then crystal frame
+    T bs[6], b[6], sc[6];
+    cubic_mul(ci_d, ci_o, ci_s, lam, bs);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bs[k] += e[k] - ep[k];
+    to_crystal(R, bs, b);
+
+    int nit = 0, fail = 0;
+    if constexpr (MODE == MODE_NEWTON) {
+      to_crystal(R, lam, sc);
+      T w[12], r[6], phi;
+      local_residual(M, sc, b, tauc, itauc, w, r, phi);
+      const T cj = T(M.c1) * T(M.n) * itauc;
+      const T ntol2 = T(M.ntol) * T(M.ntol);
+      bool conv = false;
+#pragma unroll 1
+      for (int it = 0; it < M.newton_max; ++it) {
+        T J[21], d[6], mr[6];
+        local_jacobian(M, w, cj, J);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) mr[k] = -r[k];
+        ldl_solve(J, mr, d);
+        T slope = T(0), rn2 = T(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          slope += r[k] * d[k];
+          rn2 += r[k] * r[k];
+        }
+        T step = T(1), cand[6], r1[6], phi1;
+#pragma unroll 1
+        for (int ls = 0; ls < 40; ++ls) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * d[k];
+          local_residual(M, cand, b, tauc, itauc, w, r1, phi1);
+          T rn1 = T(0);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) rn1 += r1[k] * r1[k];
+          if (isfinite(phi1) && (phi1 <= phi + T(1e-4) * step * slope || rn1 <= T(0.25) * rn2)) break;
+          step *= T(0.5);
+        }
+        T dn2 = T(0), sn2 = T(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const T dk = cand[k] - sc[k];
+          dn2 += dk * dk;
+          sc[k] = cand[k];
+          r[k] = r1[k];
+          sn2 += cand[k] * cand[k];
+        }
+        phi = phi1;
+        nit = it + 1;
+        if (dn2 <= ntol2 * fmax(sn2, T(1))) {
+          conv = true;
+          break;
+        }
+      }
+      fail = conv ? 0 : 1;
+    } else {  // MODE_TANGENT: linear solve with the tangent at the given stress
+      T st[6], w[12], g6[6], visc, asum, J[21];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) st[k] = a.sig_t[(size_t)k * vox + g];
+      to_crystal(R, st, sc);
+      flow_eval(sc, itauc, T(M.n), M.n_int, w, g6, visc, asum);
+      local_jacobian(M, w, T(M.c1) * T(M.n) * itauc, J);
+      ldl_solve(J, b, sc);
+      nit = 1;
+    }
+
+    // back to the sample frame; eps = e - C0^-1 (sigma - lam); tau = sigma - C0 eps
+    T sig[6], dsl[6], err[6], tau[6];
+    to_sample(R, sc, sig);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dsl[k] = sig[k] - lam[k];
+    cubic_mul(ci_d, ci_o, ci_s, dsl, err);
+    T tr = T(0), eps[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      eps[k] = e[k] - err[k];
+      if (k < 3) tr += eps[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tau[k] = sig[k] - c0m2 * eps[k] - (k < 3 ? c0l * tr : T(0));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.sig[(size_t)k * vox + g] = sig[k];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) sh[(p * S::LPB + l) * S::LS + x] = {tau[2 * p], tau[2 * p + 1]};
+
+    double e2 = 0.0, se = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      e2 += (double)err[k] * (double)err[k];
+      se += (double)sig[k] * (double)e[k];
+      part[1 + k] += (double)sig[k];
+    }
+    part[0] += e2;
+    part[7] += se;
+    part[8] += (double)fail;
+    part[9] = fmax(part[9], (double)nit);
+  }
+  __syncthreads();
+  fft_lines<T, N0, false, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
+
+  // unpack: Xa[k] = (Z[k] + conj Z[N-k]) / 2, Xb[k] = (Z[k] - conj Z[N-k]) / 2i
+  for (int idx = threadIdx.x; idx < 3 * S::LPB * S::H; idx += S::NT) {
+    const int p = idx / (S::LPB * S::H);
+    const int rem = idx - p * (S::LPB * S::H);
+    const int l = rem / S::H, k = rem - l * S::H;
+    const cx<T>* Z = sh + (p * S::LPB + l) * S::LS;
+    const cx<T> zk = Z[k], zm = Z[(N0 - k) & (N0 - 1)];
+    const cx<T> xa = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    const cx<T> xb = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+    const size_t line = line0 + l;
+    a.t_main[(size_t)(2 * p) * (vox / 2) + line * S::H + k] = xa;
+    a.t_main[(size_t)(2 * p + 1) * (vox / 2) + line * S::H + k] = xb;
+  }
+  // x-Nyquist plane of the next strain: e = -C0^-1 tau_hat / n0 (real)
+  if (threadIdx.x < S::LPB) {
+    const int l = threadIdx.x;
+    T tn[6], en[6];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const cx<T> z = sh[(p * S::LPB + l) * S::LS + S::H];
+      tn[2 * p] = z.x;
+      tn[2 * p + 1] = z.y;
+    }
+    cubic_mul(ci_d, ci_o, ci_s, tn, en);
+    const T s = -T(M.inv_n0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.e_nyq_next[(size_t)k * planes + line0 + l] = s * en[k];
+  }
+  block_reduce<NPART, 1>(part, a.partial + (size_t)blockIdx.x * NPART);
+}
+
+// ---------------------------------------------------------------------------
+// y pass: FFT along y of tiles of TX consecutive x-frequencies
+// ---------------------------------------------------------------------------
+template <typename T, int N1, int TX, bool INV>
+__global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
+  if (a.ctl && a.ctl->done) return;
+  constexpr int LS = N1 + 1;
+  __shared__ cx<T> sh[TX * LS];
+  const int H = a.h;
+  const size_t base = (size_t)blockIdx.y * N1 * H + (size_t)blockIdx.x * TX;
+  const cx<T>* __restrict__ src = a.src + base;
+  cx<T>* __restrict__ dst = a.dst + base;
+  for (int idx = threadIdx.x; idx < N1 * TX; idx += 256) {
+    const int y = idx / TX, kx = idx - (idx / TX) * TX;
+    sh[kx * LS + y] = src[(size_t)y * H + kx];
+  }
+  __syncthreads();
+  fft_lines<T, N1, INV, TX, LS, 256>(sh, a.tw);
+  for (int idx = threadIdx.x; idx < N1 * TX; idx += 256) {
+    const int y = idx / TX, kx = idx - (idx / TX) * TX;
+    dst[(size_t)y * H + kx] = sh[kx * LS + y];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z pass with the Green operator of the isotropic reference medium
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void apply_gamma(cx<T> (&t)[6], T nx, T ny, T nz, T c_mu, T c_ratio) {
+  // v = tau n;  w = (v - ratio (n.v) n) / mu0;  e = -sym(n (x) w)   (Mandel)
+  const T h = T(kIR2);
+  cx<T> v[3];
+  // tensor components: T11=t0, T22=t1, T33=t2, T23=h t3, T13=h t4, T12=h t5
+  v[0] = {t[0].x * nx + h * (t[5].x * ny + t[4].x * nz), t[0].y * nx + h * (t[5].y * ny + t[4].y * nz)};
+  v[1] = {h * t[5].x * nx + t[1].x * ny + h * t[3].x * nz, h * t[5].y * nx + t[1].y * ny + h * t[3].y * nz};
+  v[2] = {h * (t[4].x * nx + t[3].x * ny) + t[2].x * nz, h * (t[4].y * nx + t[3].y * ny) + t[2].y * nz};
+  const cx<T> nv = {v[0].x * nx + v[1].x * ny + v[2].x * nz, v[0].y * nx + v[1].y * ny + v[2].y * nz};
+  const T nn[3] = {nx, ny, nz};
+  cx<T> w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    w[i] = {c_mu * (v[i].x - c_ratio * nv.x * nn[i]), c_mu * (v[i].y - c_ratio * nv.y * nn[i])};
+  const T r2 = T(kR2) * T(0.5);
+  t[0] = {-nx * w[0].x, -nx * w[0].y};
+  t[1] = {-ny * w[1].x, -ny * w[1].y};
+  t[2] = {-nz * w[2].x, -nz * w[2].y};
+  t[3] = {-r2 * (ny * w[2].x + nz * w[1].x), -r2 * (ny * w[2].y + nz * w[1].y)};
+  t[4] = {-r2 * (nx * w[2].x + nz * w[0].x), -r2 * (nx * w[2].y + nz * w[0].y)};
+  t[5] = {-r2 * (nx * w[1].x + ny * w[0].x), -r2 * (nx * w[1].y + ny * w[0].y)};
+}
+
+template <typename T, int N2, int TX>
+__global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
+  if (a.ctl && a.ctl->done) return;
+  constexpr int LS = N2 + 1;
+  __shared__ cx<T> sh[6 * TX * LS];
+  const int H = a.h, n1 = a.n1;
+  const size_t cs = (size_t)N2 * n1 * H;  // component stride (complex)
+  const int ky = blockIdx.y, kx0 = blockIdx.x * TX;
+  cx<T>* __restrict__ buf = a.buf + (size_t)ky * H + kx0;
+  const size_t zs = (size_t)n1 * H;
+  for (int idx = threadIdx.x; idx < 6 * N2 * TX; idx += 256) {
+    const int c = idx / (N2 * TX);
+    const int rem = idx - c * (N2 * TX);
+    const int z = rem / TX, kx = rem - (rem / TX) * TX;
+    sh[(c * TX + kx) * LS + z] = buf[c * cs + z * zs + kx];
+  }
+  __syncthreads();
+  fft_lines<T, N2, false, 6 * TX, LS, 256>(sh, a.tw);
+
+  const T inv_n = T(a.inv_ntot);
+  const T c_mu = T(1.0 / a.c0m), c_ratio = T((a.c0l + a.c0m) / (a.c0l + 2.0 * a.c0m));
+  const T ci_d = T(a.ci_d), ci_o = T(a.ci_o), ci_s = T(a.ci_s);
+  const int ky_s = ky < n1 / 2 ? ky : ky - n1;
+  const bool nyq_y = (2 * ky == n1);
+  for (int idx = threadIdx.x; idx < N2 * TX; idx += 256) {
+    const int z = idx / TX, kx = idx - (idx / TX) * TX;
+    const int kz_s = z < N2 / 2 ? z : z - N2;
+    cx<T> t[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) t[c] = sh[(c * TX + kx) * LS + z];
+    const int kxg = kx0 + kx;
+    if (kxg == 0 && ky == 0 && z == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t[c] = {T(a.ctl->E[c]), T(0)};
+    } else if (nyq_y || 2 * z == N2) {
+      cx<T> o[6];
+      T re[6], im[6], ro[6], io[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        re[c] = t[c].x;
+        im[c] = t[c].y;
+      }
+      cubic_mul(ci_d, ci_o, ci_s, re, ro);
+      cubic_mul(ci_d, ci_o, ci_s, im, io);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = {-inv_n * ro[c], -inv_n * io[c]};
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t[c] = o[c];
+    } else {
+      const T fx = T(kxg) * T(a.inv_n0), fy = T(ky_s) * T(a.inv_n1), fz = T(kz_s) * T(a.inv_n2);
+      const T in = T(1) / sqrt(fx * fx + fy * fy + fz * fz);
+      apply_gamma(t, fx * in, fy * in, fz * in, c_mu, c_ratio);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t[c] = {inv_n * t[c].x, inv_n * t[c].y};
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sh[(c * TX + kx) * LS + z] = t[c];
+  }
+  __syncthreads();
+  fft_lines<T, N2, true, 6 * TX, LS, 256>(sh, a.tw);
+  for (int idx = threadIdx.x; idx < 6 * N2 * TX; idx += 256) {
+    const int c = idx / (N2 * TX);
+    const int rem = idx - c * (N2 * TX);
+    const int z = rem / TX, kx = rem - (rem / TX) * TX;
+    buf[c * cs + z * zs + kx] = sh[(c * TX + kx) * LS + z];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: one block
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  double v[NPART];
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < a.nblocks; b += 256) {
+    const double* p = a.partial + (size_t)b * NPART;
+#pragma unroll
+    for (int k = 0; k < NPART - 1; ++k) v[k] += p[k];
+    v[NPART - 1] = fmax(v[NPART - 1], p[NPART - 1]);
+  }
+  __shared__ double tot[NPART];
+  block_reduce<NPART, 1>(v, tot);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double iv = 1.0 / a.nvox;
+  double Sig[6], nE = 0.0, nS = 0.0, nb = 0.0, dS[6];
+  for (int k = 0; k < 6; ++k) {
+    Sig[k] = tot[1 + k] * iv;
+    nE += ctl->E[k] * ctl->E[k];
+    nS += Sig[k] * Sig[k];
+    dS[k] = a.strain_ctrl[k] ? 0.0 : (a.sig_star[k] - Sig[k]);
+    nb += dS[k] * dS[k];
+  }
+  const double err_c = sqrt(tot[0] * iv) / sqrt(nE);
+  const double err_bc = nS > 0.0 ? sqrt(nb / nS) : (nb == 0.0 ? 0.0 : INFINITY);
+  for (int k = 0; k < 6; ++k) ctl->Sigma[k] = Sig[k];
+  ctl->err_c = err_c;
+  ctl->err_bc = err_bc;
+  ctl->se = tot[7] * iv;
+  ctl->nfail = tot[8];
+  ctl->nmax = tot[9];
+  ctl->iters += 1;
+  if (!isfinite(err_c) || isnan(err_bc) || !isfinite(nS)) {
+    ctl->done = 2;
+  } else if (err_c < a.tol && err_bc < a.tol) {
+    ctl->done = 1;
+  } else {
+    for (int i = 0; i < 6; ++i) {
+      if (a.strain_ctrl[i]) continue;
+      double s = 0.0;
+      for (int j = 0; j < 6; ++j) s += a.css[6 * i + j] * dS[j];
+      ctl->E[i] += s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// end-of-increment state update (FP64 arithmetic in both precisions)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
+  const size_t V = a.nvox;
+  double part[2] = {0.0, 0.0};
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double R[9], s[6], sc[6];
+    quat_rot<double>(a.quat[g], a.quat[V + g], a.quat[2 * V + g], a.quat[3 * V + g], R);
+    for (int k = 0; k < 6; ++k) s[k] = a.sig[k * V + g];
+    to_crystal(R, s, sc);
+    const double rho = a.rho[g];
+    const double tauc = a.m.tau0 + a.m.taylor * sqrt(rho);
+    double w[12], gk[6], visc, asum;
+    flow_eval(sc, 1.0 / tauc, a.m.n, a.m.n_int, w, gk, visc, asum);
+    double dpc[6], dp[6];
+    for (int k = 0; k < 6; ++k) dpc[k] = a.gdot0 * (k < 3 ? kUN : kUS) * gk[k];
+    to_sample(R, dpc, dp);
+    for (int k = 0; k < 6; ++k) a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
+    const double rn = rho + a.dt * (a.k1 * sqrt(rho) - a.k2 * rho) * a.gdot0 * asum;
+    a.rho[g] = (T)rn;
+    part[0] += (double)(T)rn;
+    part[1] += a.gdot0 * asum;
+  }
+  block_reduce<2, 0>(part, a.partial + (size_t)blockIdx.x * 2);
+}
+
+__global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ p, int n, double* out) {
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < n; b += 256) {
+    v[0] += p[2 * b];
+    v[1] += p[2 * b + 1];
+  }
+  block_reduce<2, 0>(v, out);
+}
+
+// ---------------------------------------------------------------------------
+// set-up, validation and field export
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ingest(const double* __restrict__ q, const double* __restrict__ rho,
+                                                T* __restrict__ qo, T* __restrict__ ro, size_t V,
+                                                double* partial) {
+  double bad[2] = {0.0, 0.0};
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double c[4], n2 = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      c[k] = q[k * V + g];
+      n2 += c[k] * c[k];
+    }
+    const double nrm = sqrt(n2);
+    if (!(fabs(nrm - 1.0) <= 1e-6)) bad[0] += 1.0;
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int k = 0; k < 4; ++k) qo[k * V + g] = (T)(c[k] * inv);
+    const double r = rho[g];
+    if (!(r > 0.0 && isfinite(r))) bad[1] += 1.0;
+    ro[g] = (T)r;
+  }
+  block_reduce<2, 0>(bad, partial + (size_t)blockIdx.x * 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_export(const T* __restrict__ src, double* __restrict__ dst, size_t V,
+                                                int ncomp, int mandel) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V * ncomp; g += (size_t)gridDim.x * 256) {
+    const int c = (int)(g / V);
+    const double f = (mandel && c >= 3) ? kIR2 : 1.0;
+    dst[g] = f * (double)src[g];
+  }
+}
+
+// add a uniform strain to the x-DC coefficient of every x-line
+template <typename T>
+__global__ __launch_bounds__(256) void k_shift_dc(cx<T>* main, size_t planes, int h, Shift6 d) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < 6 * planes; g += (size_t)gridDim.x * 256) {
+    const int c = (int)(g / planes);
+    const size_t line = g - c * planes;
+    main[(size_t)c * planes * h + line * h].x += (T)d.v[c];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* p, size_t n, T v) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (size_t)gridDim.x * 256) p[g] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+template <typename T, int MODE>
+hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s) {
+  const int planes = a.n1 * a.n2;
+#define FFTEVP_LOCAL(N)                                                         \
+  case N: {                                                                     \
+    const int lpb = LocalShape<T, N>::LPB;                                      \
+    hipLaunchKernelGGL((k_local<T, N, MODE>), dim3(planes / lpb), dim3(256), 0, s, a); \
+    break;                                                                      \
+  }
+  switch (n0) {
+    FFTEVP_LOCAL(8)
+    FFTEVP_LOCAL(16)
+    FFTEVP_LOCAL(32)
+    FFTEVP_LOCAL(64)
+    FFTEVP_LOCAL(128)
+    FFTEVP_LOCAL(256)
+    FFTEVP_LOCAL(512)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef FFTEVP_LOCAL
+  return hipGetLastError();
+}
+
+template <typename T>
+int local_blocks(int n0, int n1, int n2) {
+  const int lpb = n0 >= 256 ? 1 : 256 / n0;
+  return n1 * n2 / lpb;
+}
+
+// Launch with the largest tile TX <= TXM that divides the h x-frequencies.
+template <typename T, int N, int TX, bool INV>
+hipError_t ypass_tx(int n2, const YArgs<T>& a, hipStream_t s) {
+  if constexpr (TX > 1) {
+    if (a.h < TX) return ypass_tx<T, N, TX / 2, INV>(n2, a, s);
+  }
+  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, 6 * n2), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool INV>
+hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s) {
+  // 16 B (FP64) or 8 B (FP32) complex: 256 B rows, LDS <= 64 KB
+  constexpr int B = sizeof(T) == 8 ? 16 : 32;
+  switch (n1) {
+    case 8: return ypass_tx<T, 8, B, INV>(n2, a, s);
+    case 16: return ypass_tx<T, 16, B, INV>(n2, a, s);
+    case 32: return ypass_tx<T, 32, B, INV>(n2, a, s);
+    case 64: return ypass_tx<T, 64, B, INV>(n2, a, s);
+    case 128: return ypass_tx<T, 128, B, INV>(n2, a, s);
+    case 256: return ypass_tx<T, 256, B, INV>(n2, a, s);
+    case 512: return ypass_tx<T, 512, B / 2, INV>(n2, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+constexpr int z_tile(int n2) {
+  // six components of TX z-lines in LDS: 6 * TX * (n2 + 1) complex <= ~100 KB
+  int tx = 16;
+  while (tx > 1 && 6 * tx * (n2 + 1) * 2 * (int)sizeof(T) > 100 * 1024) tx /= 2;
+  return tx;
+}
+
+template <typename T, int N, int TX>
+hipError_t zgamma_tx(const ZArgs<T>& a, hipStream_t s) {
+  if constexpr (TX > 1) {
+    if (a.h < TX) return zgamma_tx<T, N, TX / 2>(a, s);
+  }
+  hipLaunchKernelGGL((k_zgamma<T, N, TX>), dim3(a.h / TX, a.n1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s) {
+  switch (n2) {
+    case 8: return zgamma_tx<T, 8, z_tile<T>(8)>(a, s);
+    case 16: return zgamma_tx<T, 16, z_tile<T>(16)>(a, s);
+    case 32: return zgamma_tx<T, 32, z_tile<T>(32)>(a, s);
+    case 64: return zgamma_tx<T, 64, z_tile<T>(64)>(a, s);
+    case 128: return zgamma_tx<T, 128, z_tile<T>(128)>(a, s);
+    case 256: return zgamma_tx<T, 256, z_tile<T>(256)>(a, s);
+    case 512: return zgamma_tx<T, 512, z_tile<T>(512)>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_state<T>, dim3(nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, (const double*)a.partial, nblocks, out2);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
+                         int nblocks, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_ingest<T>, dim3(nblocks), dim3(256), 0, s, q, rho, qo, ro, V, partial);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, (const double*)partial, nblocks, out2);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_export(const T* src, double* dst, size_t V, int ncomp, int mandel, hipStream_t s) {
+  hipLaunchKernelGGL(k_export<T>, dim3(grid_for(V * ncomp)), dim3(256), 0, s, src, dst, V, ncomp, mandel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_shift_dc(cx<T>* main, size_t planes, int h, const double dE[6], hipStream_t s) {
+  Shift6 d;
+  for (int k = 0; k < 6; ++k) d.v[k] = dE[k];
+  hipLaunchKernelGGL(k_shift_dc<T>, dim3(grid_for(6 * planes)), dim3(256), 0, s, main, planes, h, d);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+#define FFTEVP_INST(T)                                                                          \
+  template hipError_t launch_local<T, MODE_NEWTON>(int, const LocalArgs<T>&, hipStream_t);     \
+  template hipError_t launch_local<T, MODE_TANGENT>(int, const LocalArgs<T>&, hipStream_t);    \
+  template hipError_t launch_local<T, MODE_EXPORT>(int, const LocalArgs<T>&, hipStream_t);     \
+  template int local_blocks<T>(int, int, int);                                                  \
+  template hipError_t launch_ypass<T, false>(int, int, const YArgs<T>&, hipStream_t);          \
+  template hipError_t launch_ypass<T, true>(int, int, const YArgs<T>&, hipStream_t);           \
+  template hipError_t launch_zgamma<T>(int, const ZArgs<T>&, hipStream_t);                     \
+  template hipError_t launch_state<T>(const StateArgs<T>&, int, double*, hipStream_t);         \
+  template hipError_t launch_ingest<T>(const double*, const double*, T*, T*, size_t, double*, int, \
+                                       double*, hipStream_t);                                  \
+  template hipError_t launch_export<T>(const T*, double*, size_t, int, int, hipStream_t);      \
+  template hipError_t launch_shift_dc<T>(cx<T>*, size_t, int, const double*, hipStream_t);     \
+  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
+
+FFTEVP_INST(double)
+FFTEVP_INST(float)
+
+}  // namespace fftevp

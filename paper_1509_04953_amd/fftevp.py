@@ -1,0 +1,247 @@
+"""Python binding of ``libfftevp.so`` (ctypes).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels. PyTorch supplies device memory (tensors whose ``data_ptr`` is handed
+to the library) and the stream (``torch.cuda.current_stream()``). There is no
+CPU fallback: if the library or a GPU is missing, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "libfftevp.so"
+_lib = None
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENONFINITE, ELOCAL, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5}
+NPROF = 7
+PROF_NAMES = ("local", "finalize", "yfwd", "zgamma", "yinv", "state", "adjoint_setup")
+NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6}
+
+
+class Cubic(C.Structure):
+    _fields_ = [("C11", C.c_double), ("C12", C.c_double), ("C44", C.c_double)]
+
+
+class FlowC(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("tau0", "k1", "k2", "n", "gdot0", "alpha", "mu", "b")]
+
+
+class LoadingC(C.Structure):
+    _fields_ = [("Edot", C.c_double * 6), ("Sigma", C.c_double * 6),
+                ("strain_ctrl", C.c_int * 6), ("dt", C.c_double)]
+
+
+class OptsC(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("newton_max", C.c_int),
+                ("c0_lambda", C.c_double), ("c0_mu", C.c_double)]
+
+
+class ReportC(C.Structure):
+    _fields_ = [("iters", C.c_int), ("newton_max_seen", C.c_int), ("newton_failed", C.c_int),
+                ("err_c", C.c_double), ("err_bc", C.c_double), ("Sigma", C.c_double * 6),
+                ("E", C.c_double * 6), ("rho_mean", C.c_double)]
+
+
+def library():
+    """Load ``libfftevp.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise RuntimeError(f"{_LIB_PATH} is missing: run `python -m paper_1509_04953_amd.build`")
+    lib = C.CDLL(str(_LIB_PATH))
+    P, I, D, S = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_size_t
+    sig = {
+        "fftevp_create": (I, [I, I, I, I, P, C.POINTER(P)]),
+        "fftevp_destroy": (I, [P]),
+        "fftevp_set_material": (I, [P, C.POINTER(Cubic), C.POINTER(FlowC)]),
+        "fftevp_set_microstructure": (I, [P, P, P]),
+        "fftevp_set_loading": (I, [P, C.POINTER(LoadingC)]),
+        "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
+        "fftevp_get_field": (I, [P, I, P]),
+        "fftevp_state_bytes": (S, [P]),
+        "fftevp_save_state": (I, [P, P]),
+        "fftevp_load_state": (I, [P, P]),
+        "fftevp_adjoint_bytes": (S, [P]),
+        "fftevp_adjoint_increment": (I, [P, C.POINTER(OptsC), P, P, D, P, D]),
+        "fftevp_set_profiling": (I, [P, I]),
+        "fftevp_get_profile": (I, [P, D, C.POINTER(C.c_longlong), I]),
+        "fftevp_status_string": (C.c_char_p, [I]),
+        "fftevp_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FftevpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fftevp status {status}: {msg}")
+        self.status = status
+
+
+@dataclass
+class Material:
+    C11: float = 168400.0
+    C12: float = 121400.0
+    C44: float = 75400.0
+    tau0: float = 5.0
+    k1: float = 8.0e7
+    k2: float = 10.0
+    n: float = 10.0
+    gdot0: float = 1.0e-3
+    alpha: float = 0.5
+    mu: float = 47337.0
+    b: float = 2.56e-10
+
+    def theta(self):
+        return np.array([self.tau0, self.k1, self.k2, self.n])
+
+
+@dataclass
+class Load:
+    Edot: tuple = (0.0, 0.0, -1.0e-3, 0.0, 0.0, 0.0)
+    Sigma: tuple = (0.0,) * 6
+    strain_ctrl: tuple = (0, 0, 1, 0, 0, 0)
+    dt: float = 2.0
+
+
+@dataclass
+class Opts:
+    tol: float = 1e-6
+    max_iter: int = 1000
+    newton_max: int = 50
+    c0_lambda: float = 0.0
+    c0_mu: float = 0.0
+
+
+@dataclass
+class Report:
+    status: int
+    iters: int
+    newton_max_seen: int
+    newton_failed: int
+    err_c: float
+    err_bc: float
+    Sigma: np.ndarray
+    E: np.ndarray
+    rho_mean: float
+    extra: dict = field(default_factory=dict)
+
+
+def _opts(o: Opts | None):
+    o = o or Opts()
+    return OptsC(o.tol, o.max_iter, o.newton_max, o.c0_lambda, o.c0_mu)
+
+
+class Solver:
+    """One FFT-EVP context on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, shape, precision: str = "fp64", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("fftevp needs a GPU; no CPU fallback exists")
+        self.torch = torch
+        self.lib = library()
+        self.shape = tuple(int(s) for s in shape)
+        self.nvox = int(np.prod(self.shape))
+        self.precision = precision
+        prec = {"fp64": FP64, "mixed": MIXED}[precision]
+        self.stream = stream or torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = self.lib.fftevp_create(*self.shape, prec, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise FftevpError(st, self.lib.fftevp_status_string(st).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fftevp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise FftevpError(st, self.lib.fftevp_last_error(self.h).decode())
+        return st
+
+    def set_material(self, m: Material):
+        self._check(self.lib.fftevp_set_material(self.h, C.byref(Cubic(m.C11, m.C12, m.C44)),
+                                                 C.byref(FlowC(m.tau0, m.k1, m.k2, m.n, m.gdot0,
+                                                               m.alpha, m.mu, m.b))))
+        self.material = m
+
+    def _dev(self, a, shape):
+        t = self.torch.as_tensor(a, dtype=self.torch.float64, device="cuda").reshape(shape).contiguous()
+        return t
+
+    def set_microstructure(self, quat, rho):
+        q = self._dev(quat, (4, self.nvox))
+        r = self._dev(rho, (self.nvox,))
+        self._check(self.lib.fftevp_set_microstructure(self.h, C.c_void_p(q.data_ptr()),
+                                                       C.c_void_p(r.data_ptr())))
+
+    def set_loading(self, ld: Load):
+        c = LoadingC((C.c_double * 6)(*ld.Edot), (C.c_double * 6)(*ld.Sigma),
+                     (C.c_int * 6)(*ld.strain_ctrl), ld.dt)
+        self._check(self.lib.fftevp_set_loading(self.h, C.byref(c)))
+
+    def step(self, opts: Opts | None = None, allow=(OK, NOT_CONVERGED, ELOCAL)) -> Report:
+        r = ReportC()
+        st = self._check(self.lib.fftevp_step(self.h, C.byref(_opts(opts)), C.byref(r)), allow)
+        return Report(st, r.iters, r.newton_max_seen, r.newton_failed, r.err_c, r.err_bc,
+                      np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean)
+
+    def field(self, name: str):
+        n = NCOMP[name]
+        out = self.torch.empty((n, self.nvox) if n > 1 else (self.nvox,), dtype=self.torch.float64,
+                               device="cuda")
+        self._check(self.lib.fftevp_get_field(self.h, FIELDS[name], C.c_void_p(out.data_ptr())))
+        return out
+
+    def state_bytes(self) -> int:
+        return int(self.lib.fftevp_state_bytes(self.h))
+
+    def save_state(self, out=None):
+        if out is None:
+            out = self.torch.empty(self.state_bytes(), dtype=self.torch.uint8, device="cuda")
+        self._check(self.lib.fftevp_save_state(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def load_state(self, buf):
+        self._check(self.lib.fftevp_load_state(self.h, C.c_void_p(buf.data_ptr())))
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.fftevp_set_profiling(self.h, int(bool(on))))
+
+    def profile(self, reset=True):
+        """Per kernel class: (summed ms, launches) from HIP events."""
+        ms = (C.c_double * NPROF)()
+        n = (C.c_longlong * NPROF)()
+        self._check(self.lib.fftevp_get_profile(self.h, ms, n, int(reset)))
+        return {name: (ms[k], n[k]) for k, name in enumerate(PROF_NAMES)}
+
+    def adjoint_bytes(self) -> int:
+        return int(self.lib.fftevp_adjoint_bytes(self.h))
+
+    def adjoint_increment(self, before, after, dL_dSigma, adj, dtheta, opts: Opts | None = None):
+        g = (C.c_double * 6)(*[float(x) for x in dL_dSigma])
+        th = (C.c_double * 4)(*[float(x) for x in dtheta])
+        self._check(self.lib.fftevp_adjoint_increment(
+            self.h, C.byref(_opts(opts)), C.c_void_p(before.data_ptr()), C.c_void_p(after.data_ptr()),
+            g, C.c_void_p(adj.data_ptr()), th))
+        return np.array(th[:])

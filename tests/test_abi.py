@@ -1,0 +1,61 @@
+"""The C ABI: the library loads and exports every declared symbol; argument
+checks that return before any device work behave as documented. No GPU."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "fftevp.h"
+LIB = ROOT / "paper_1509_04953_amd" / "libfftevp.so"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not LIB.exists():
+        pytest.fail(f"{LIB} not built: run `python -m paper_1509_04953_amd.build`")
+    from paper_1509_04953_amd import library
+    return library()
+
+
+def declared():
+    text = HEADER.read_text()
+    return sorted(set(re.findall(r"\b(fftevp_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for s in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert lib.fftevp_status_string(s)
+    assert lib.fftevp_status_string(1) == b"not converged"
+
+
+@pytest.mark.parametrize("dims", [(0, 16, 16), (12, 16, 16), (16, 1024, 16), (16, 16, 4), (16, 16, -8)])
+def test_create_rejects_bad_grids(lib, dims):
+    h = C.c_void_p()
+    assert lib.fftevp_create(*dims, 0, None, C.byref(h)) == -1
+    assert not h.value
+
+
+def test_create_rejects_bad_precision_and_null_out(lib):
+    h = C.c_void_p()
+    assert lib.fftevp_create(16, 16, 16, 7, None, C.byref(h)) == -1
+    assert lib.fftevp_create(16, 16, 16, 0, None, None) == -1
+
+
+def test_null_context_calls(lib):
+    assert lib.fftevp_step(None, None, None) == -1
+    assert lib.fftevp_destroy(None) == -1
+    assert lib.fftevp_set_material(None, None, None) == -1
+    assert lib.fftevp_set_loading(None, None) == -1
+    assert lib.fftevp_get_field(None, 0, None) == -1
+    assert lib.fftevp_state_bytes(None) == 0
+    assert lib.fftevp_set_profiling(None, 1) == -1
+    assert lib.fftevp_last_error(None) == b"null context"
