@@ -110,10 +110,13 @@ typedef struct {
  *   err_c   rms_x |e - eps| / |E|   (compatibility vs. constitutive strain)
  *   err_bc  |(Sigma* - <sigma>)_s| / |<sigma>| over stress-controlled comps
  *   Sigma   volume-averaged stress of the last iterate, E the mean strain
- *   rho_mean mean density after the state update (unchanged if not committed) */
+ *   rho_mean mean density after the state update (unchanged if not committed)
+ *   newton_mean, linesearch_mean  Newton iterations and line-search halvings
+ *           per voxel in the last iteration */
 typedef struct {
   int iters, newton_max_seen, newton_failed;
   double err_c, err_bc, Sigma[6], E[6], rho_mean;
+  double newton_mean, linesearch_mean;
 } fftevp_report;
 
 /* Create a context for an n0 x n1 x n2 grid (x, y, z), each a power of two

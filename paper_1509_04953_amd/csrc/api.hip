@@ -414,7 +414,8 @@ template <typename T>
 fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* rep) {
   const C0 c0 = reference_medium(ctx, &o);
   const double dt = ctx->load.dt;
-  const Mat m = make_mat(ctx, c0, dt, sizeof(T) == 8 ? 1e-12 : 1e-5, o.newton_max);
+  Mat m = make_mat(ctx, c0, dt, sizeof(T) == 8 ? 1e-12 : 1e-5, o.newton_max);
+  m.qtol = sizeof(T) == 8 ? 1e-7 : 3e-4;
   FinArgs fin = make_fin(ctx, o, c0);
   double Edot[6], E1[6], dE[6];
   to_mandel(ctx->load.Edot, Edot);
@@ -479,6 +480,8 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     to_plain(so.ctl.Sigma, rep->Sigma);
     to_plain(so.ctl.E, rep->E);
     rep->rho_mean = rho_mean;
+    rep->newton_mean = so.ctl.nsum / (double)ctx->V;
+    rep->linesearch_mean = so.ctl.lssum / (double)ctx->V;
   }
   return ret;
 }

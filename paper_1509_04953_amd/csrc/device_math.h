@@ -52,6 +52,7 @@ struct Mat {
   int n_int;              // n if n is a positive integer, else 0
   int newton_max;
   double ntol;            // Newton step tolerance (relative)
+  double qtol;            // full Newton steps below this are final (quadratic regime)
   double tau0, taylor;    // tauc = tau0 + taylor * sqrt(rho), taylor = alpha mu b
   double inv_n0;          // 1 / n0
 };
@@ -141,49 +142,71 @@ __device__ __forceinline__ T resolved(const T (&s)[6]) {
   return T(kUN) * tn + T(kUS) * ts;
 }
 
-// |x|^(n-1) for x >= 0; integral n by repeated squaring
-template <typename T>
-__device__ __forceinline__ T pow_nm1(T ax, T n, int n_int) {
-  if (n_int > 0) {
-    T r = T(1), b = ax;
-    int e = n_int - 1;
-    while (e) {
-      if (e & 1) r *= b;
-      b *= b;
-      e >>= 1;
-    }
-    return r;
-  }
-  return ax > T(0) ? exp((n - T(1)) * log(ax)) : (n == T(1) ? T(1) : T(0));
-}
-
 // Flow at a crystal-frame stress s:
 //   w[a]  = |x_a|^(n-1),  x_a = tau_a / tauc
 //   g[k]  = sum_a sign(x_a)|x_a|^n kSign[a][k]   (epsdot_p = gdot0 * u_k g[k])
 //   visc  = sum_a |x_a|^(n+1)
 //   asum  = sum_a |x_a|^n
-template <typename T>
+// INTN: n is a positive integer (n_int); the powers then come from a
+// binary-exponent loop with a uniform trip count. Otherwise
+// |x|^(n-1) = exp((n-1) log|x|). Systems are processed four at a time to
+// bound the number of live registers.
+template <bool INTN, int G, typename T>
+__device__ __forceinline__ void flow_group(const T (&s)[6], T itauc, T n, int n_int, T (&w)[12],
+                                           T (&g)[6], T& visc, T& asum) {
+  T x[4], wg[4];
+  static_for<0, 4>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    x[A] = resolved<4 * G + A>(s) * itauc;
+  });
+  if constexpr (INTN) {
+    T base[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      base[a] = fabs(x[a]);
+      wg[a] = T(1);
+    }
+#pragma unroll 1
+    for (int e = n_int - 1; e != 0; e >>= 1) {
+      if (e & 1) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wg[a] *= base[a];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) base[a] *= base[a];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const T ax = fabs(x[a]);
+      wg[a] = ax > T(0) ? exp((n - T(1)) * log(ax)) : (n == T(1) ? T(1) : T(0));
+    }
+  }
+  static_for<0, 4>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    const T ax = fabs(x[A]);
+    const T p = wg[A] * ax;
+    w[4 * G + A] = wg[A];
+    visc += p * ax;
+    asum += p;
+    const T sp = x[A] < T(0) ? -p : p;
+    static_for<0, 6>([&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      acc_sign<kSign[4 * G + A][K]>(g[K], sp);
+    });
+  });
+}
+
+template <bool INTN, typename T>
 __device__ __forceinline__ void flow_eval(const T (&s)[6], T itauc, T n, int n_int, T (&w)[12],
                                           T (&g)[6], T& visc, T& asum) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = T(0);
   visc = T(0);
   asum = T(0);
-  static_for<0, 12>([&](auto ac) {
-    constexpr int A = decltype(ac)::value;
-    const T x = resolved<A>(s) * itauc;
-    const T ax = fabs(x);
-    const T wa = pow_nm1(ax, n, n_int);
-    const T p = wa * ax;
-    w[A] = wa;
-    visc += p * ax;
-    asum += p;
-    const T sp = x < T(0) ? -p : p;
-    static_for<0, 6>([&](auto kc) {
-      constexpr int K = decltype(kc)::value;
-      acc_sign<kSign[A][K]>(g[K], sp);
-    });
-  });
+  flow_group<INTN, 0>(s, itauc, n, n_int, w, g, visc, asum);
+  flow_group<INTN, 1>(s, itauc, n, n_int, w, g, visc, asum);
+  flow_group<INTN, 2>(s, itauc, n, n_int, w, g, visc, asum);
 }
 
 // cubic-form 6x6 (Mandel) times vector: normal block (d, o), shear diag s
@@ -200,11 +223,11 @@ __device__ __forceinline__ void cubic_mul(T d, T o, T sh, const T (&v)[6], T (&o
 // residual and potential of the local problem in the crystal frame:
 //   r   = A s - b + c1 * m(g)
 //   phi = 1/2 s.A s - b.s + c1 tauc/(n+1) visc
-template <typename T>
+template <bool INTN, typename T>
 __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], const T (&b)[6],
                                                T tauc, T itauc, T (&w)[12], T (&r)[6], T& phi) {
   T g[6], visc, asum;
-  flow_eval(s, itauc, T(M.n), M.n_int, w, g, visc, asum);
+  flow_eval<INTN>(s, itauc, T(M.n), M.n_int, w, g, visc, asum);
   T As[6];
   cubic_mul(T(M.a_d), T(M.a_o), T(M.a_s), s, As);
   const T c1 = T(M.c1);
@@ -218,34 +241,26 @@ __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], co
   phi = q + c1 * tauc / (T(M.n) + T(1)) * visc;
 }
 
-// J = A + cj * sum_a w_a m_a m_a^T  (packed lower triangle, 21 entries)
-template <typename T>
-__device__ __forceinline__ void local_jacobian(const Mat& M, const T (&w)[12], T cj, T (&J)[21]) {
-  T H[21];
-#pragma unroll
-  for (int k = 0; k < 21; ++k) H[k] = T(0);
-  static_for<0, 12>([&](auto ac) {
-    constexpr int A = decltype(ac)::value;
-    static_for<0, 6>([&](auto ic) {
-      constexpr int I = decltype(ic)::value;
-      static_for<0, I + 1>([&](auto jc) {
-        constexpr int J2 = decltype(jc)::value;
-        constexpr int c = kSign[A][I] * kSign[A][J2];
-        acc_sign<c>(H[tri(I, J2)], w[A]);
+// J = A + cj * sum_a w_a m_a m_a^T  (packed lower triangle, 21 entries),
+// assembled entry by entry in precision JT.
+template <typename JT, typename T>
+__device__ __forceinline__ void local_jacobian(const Mat& M, const T (&w)[12], T cj, JT (&J)[21]) {
+  static_for<0, 6>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    static_for<0, I + 1>([&](auto jc) {
+      constexpr int J2 = decltype(jc)::value;
+      T h = T(0);
+      static_for<0, 12>([&](auto ac) {
+        constexpr int A = decltype(ac)::value;
+        acc_sign<kSign[A][I] * kSign[A][J2]>(h, w[A]);
       });
+      constexpr double f = (I < 3 && J2 < 3) ? 1.0 / 6.0 : ((I >= 3 && J2 >= 3) ? 1.0 / 12.0 : kUN * kUS);
+      T a0 = T(0);
+      if constexpr (I < 3 && J2 < 3) a0 = (I == J2) ? T(M.a_d) : T(M.a_o);
+      else if constexpr (I == J2) a0 = T(M.a_s);
+      J[tri(I, J2)] = JT(a0 + cj * T(f) * h);
     });
   });
-  const T nn = cj * T(1.0 / 6.0), ns = cj * T(kUN * kUS), ss = cj * T(1.0 / 12.0);
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      const T f = (i < 3 && j < 3) ? nn : ((i >= 3 && j >= 3) ? ss : ns);
-      T a = T(0);
-      if (i < 3 && j < 3) a = (i == j) ? T(M.a_d) : T(M.a_o);
-      else if (i == j) a = T(M.a_s);
-      J[tri(i, j)] = a + f * H[tri(i, j)];
-    }
 }
 
 // Solve J x = rhs for SPD J (packed lower triangle) by J = L D L^T with unit

@@ -10,18 +10,29 @@ namespace fftevp {
 
 enum { MODE_NEWTON = 0, MODE_TANGENT = 1, MODE_EXPORT = 2 };
 
-// per-block partial sums of the local kernel:
+// per-block partial sums of the local kernel, stored [NPART][blocks]:
 // [0] sum |e - eps|^2, [1..6] sum sigma, [7] sum sigma:e, [8] Newton failures,
-// [9] max Newton iterations (reduced by max)
-constexpr int NPART = 10;
+// [9] sum Newton iterations, [10] sum line-search halvings,
+// [11] max Newton iterations (reduced by max)
+constexpr int NPART = 12;
 
 // Device-resident control block of one increment.
 struct Ctl {
   double E[6];      // macroscopic strain (Mandel) used by the next spectral update
   double Sigma[6];  // mean stress of the latest iterate (Mandel)
-  double err_c, err_bc, se, nfail, nmax;
+  double err_c, err_bc, se, nfail, nmax, nsum, lssum;
   int done;         // 0 running, 1 converged, 2 non-finite
   int iters;        // completed local solves
+};
+
+struct FinArgs {
+  const double* partial;  // [NPART][blocks]
+  int nblocks;
+  double nvox, tol;
+  int strain_ctrl[6];
+  double sig_star[6];  // Mandel
+  double css[36];      // [(C0)_ss]^-1 embedded in 6x6 (Mandel), zero elsewhere
+  Ctl* ctl;
 };
 
 template <typename T>
@@ -36,7 +47,7 @@ struct LocalArgs {
   const T* rho;         // density, [V]
   const T* quat;        // orientation, [4][V]
   const T* sig_t;       // tangent mode: stress the tangent is taken at
-  double* partial;      // [blocks][NPART]
+  double* partial;      // [NPART][blocks]
   const Ctl* ctl;
   const cx<T>* tw;      // twiddles for n0
   double* out;          // export mode: plain-component strain, [6][V] FP64
@@ -63,16 +74,6 @@ struct ZArgs {
   int h, n1;
   double inv_n0, inv_n1, inv_n2, inv_ntot;
   double c0l, c0m, ci_d, ci_o, ci_s;
-};
-
-struct FinArgs {
-  const double* partial;
-  int nblocks;
-  double nvox, tol;
-  int strain_ctrl[6];
-  double sig_star[6];  // Mandel
-  double css[36];      // [(C0)_ss]^-1 embedded in 6x6 (Mandel), zero elsewhere
-  Ctl* ctl;
 };
 
 template <typename T>

@@ -1,13 +1,14 @@
 // FFT-EVP fixed-point iteration kernels for gfx950.
 //
 // One iteration of the augmented-Lagrangian scheme (Sec. 2.1, Eq. 1-2) is
-// four passes over HBM plus a one-block reduction:
+// four passes over HBM:
 //   k_local    per x-line: inverse real FFT along x of the compatible strain
 //              (LDS), local Newton solve per voxel (registers), polarisation
 //              tau = sigma - C0:eps, forward real FFT along x (LDS); FP64
 //              partial sums of the residual and the mean stress.
-//   k_finalize one block: deterministic reduction, stop test, mixed
-//              boundary-condition update of the macroscopic strain.
+//   k_finalize one block: reduction of the partial sums in a fixed order,
+//              stop test, update of the macroscopic strain of the
+//              stress-controlled components (mixed boundary conditions).
 //   k_ypass    forward FFT along y (tiles of x-frequencies, LDS).
 //   k_zgamma   forward FFT along z, Green operator per frequency, inverse
 //              FFT along z, for all six components at once (LDS).
@@ -39,9 +40,9 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Block of 256 threads: reduce NP values (the last NMAX of them by max) and
-// write them to out[0..NP). Deterministic order.
+// write them to out[k * stride], k < NP. Deterministic order.
 template <int NP, int NMAX>
-__device__ __forceinline__ void block_reduce(double (&v)[NP], double* __restrict__ out) {
+__device__ __forceinline__ void block_reduce(double (&v)[NP], double* __restrict__ out, size_t stride = 1) {
   __shared__ double red[4][NP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -54,7 +55,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NP], double* __restrict
     const int k = threadIdx.x;
     double r = red[0][k];
     for (int w = 1; w < 4; ++w) r = (k >= NP - NMAX) ? fmax(r, red[w][k]) : r + red[w][k];
-    out[k] = r;
+    out[k * stride] = r;
   }
 }
 
@@ -101,8 +102,14 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
   }
 }
 
-template <typename T, int N0, int MODE>
-__global__ __launch_bounds__(256) void k_local(LocalArgs<T> a) {
+#ifndef FFTEVP_LOCAL_WAVES
+#define FFTEVP_LOCAL_WAVES 1
+#endif
+
+// INTN: the rate exponent is a positive integer (compile-time choice of the
+// power evaluation; the host picks the instance).
+template <typename T, int N0, int MODE, bool INTN>
+__global__ __launch_bounds__(256, FFTEVP_LOCAL_WAVES) void k_local(LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
   if (a.ctl && a.ctl->done) return;
   __shared__ cx<T> sh[3 * S::LPB * S::LS];
@@ -146,105 +153,127 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs<T> a) {
     const int t = threadIdx.x + v * S::NT;
     const int l = t / N0, x = t - (t / N0) * N0;
     const size_t g = (line0 + l) * N0 + x;
-    T e[6], lam[6], ep[6];
+    auto load_e = [&](T (&e)[6]) {
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
-      e[2 * p] = z.x;
-      e[2 * p + 1] = z.y;
-    }
-    if (a.add_dE) {
+      for (int p = 0; p < 3; ++p) {
+        const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
+        e[2 * p] = z.x;
+        e[2 * p + 1] = z.y;
+      }
+      if (a.add_dE) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) e[k] += T(a.dE[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      lam[k] = a.lam[(size_t)k * vox + g];
-      ep[k] = a.epsp[(size_t)k * vox + g];
-    }
-    T R[9];
-    {
-      const T qw = a.quat[g], qx = a.quat[vox + g], qy = a.quat[2 * vox + g], qz = a.quat[3 * vox + g];
-      quat_rot(qw, qx, qy, qz, R);
-    }
+        for (int k = 0; k < 6; ++k) e[k] += T(a.dE[k]);
+      }
+    };
+    auto rot = [&](T (&R)[9]) { quat_rot(a.quat[g], a.quat[vox + g], a.quat[2 * vox + g], a.quat[3 * vox + g], R); };
     const T tauc = T(M.tau0) + T(M.taylor) * sqrt(a.rho[g]);
     const T itauc = T(1) / tauc;
 
-    // b = C0^-1 lam + e - epsp   (sample frame), then crystal frame
-    T bs[6], b[6], sc[6];
-    cubic_mul(ci_d, ci_o, ci_s, lam, bs);
+    // b = C0^-1 lam + e - epsp in the crystal frame; start from lam
+    T b[6], sc[6];
+    {
+      T R[9], e[6], lam[6], bs[6];
+      rot(R);
+      load_e(e);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) bs[k] += e[k] - ep[k];
-    to_crystal(R, bs, b);
+      for (int k = 0; k < 6; ++k) lam[k] = a.lam[(size_t)k * vox + g];
+      cubic_mul(ci_d, ci_o, ci_s, lam, bs);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) bs[k] += e[k] - a.epsp[(size_t)k * vox + g];
+      to_crystal(R, bs, b);
+      if constexpr (MODE == MODE_NEWTON) to_crystal(R, lam, sc);
+    }
 
-    int nit = 0, fail = 0;
+    int nit = 0, fail = 0, nls = 0;
     if constexpr (MODE == MODE_NEWTON) {
-      to_crystal(R, lam, sc);
-      T w[12], r[6], phi;
-      local_residual(M, sc, b, tauc, itauc, w, r, phi);
+      // Damped Newton on the convex potential, written around one evaluation
+      // of the residual: each pass evaluates the candidate, then either
+      // halves the step (line search) or accepts it and computes the next
+      // Newton direction from the accepted point's tangent.
+      T w[12], r[6], d[6];
+      T phi = T(0), slope = T(0), rn2 = T(0), step = T(0);
       const T cj = T(M.c1) * T(M.n) * itauc;
-      const T ntol2 = T(M.ntol) * T(M.ntol);
-      bool conv = false;
+      const T ntol2 = T(M.ntol) * T(M.ntol), qtol2 = T(M.qtol) * T(M.qtol);
+      bool conv = false, first = true;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) d[k] = T(0);
 #pragma unroll 1
-      for (int it = 0; it < M.newton_max; ++it) {
-        T J[21], d[6], mr[6];
-        local_jacobian(M, w, cj, J);
+      for (int pass = 0; pass < 64 * M.newton_max; ++pass) {
+        T phi1, cand[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) mr[k] = -r[k];
-        ldl_solve(J, mr, d);
-        T slope = T(0), rn2 = T(0);
+        for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * d[k];
+        local_residual<INTN>(M, cand, b, tauc, itauc, w, r, phi1);
+        T rn1 = T(0);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          slope += r[k] * d[k];
-          rn2 += r[k] * r[k];
+        for (int k = 0; k < 6; ++k) rn1 += r[k] * r[k];
+        if (!first) {
+          const bool ok = isfinite(phi1) && (phi1 <= phi + T(1e-4) * step * slope || rn1 <= T(0.25) * rn2);
+          if (!ok && step > T(1e-12)) {
+            step *= T(0.5);
+            ++nls;
+            continue;
+          }
+          T dn2 = T(0), sn2 = T(0);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const T dk = step * d[k];
+            dn2 += dk * dk;
+            sc[k] = cand[k];
+            sn2 += cand[k] * cand[k];
+          }
+          ++nit;
+          // a full Newton step this small leaves an error of its square
+          const T sc2 = fmax(sn2, T(1));
+          if (dn2 <= ntol2 * sc2 || (step == T(1) && dn2 <= qtol2 * sc2)) {
+            conv = true;
+            break;
+          }
+          if (nit >= M.newton_max) break;
         }
-        T step = T(1), cand[6], r1[6], phi1;
-#pragma unroll 1
-        for (int ls = 0; ls < 40; ++ls) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * d[k];
-          local_residual(M, cand, b, tauc, itauc, w, r1, phi1);
-          T rn1 = T(0);
-#pragma unroll
-          for (int k = 0; k < 6; ++k) rn1 += r1[k] * r1[k];
-          if (isfinite(phi1) && (phi1 <= phi + T(1e-4) * step * slope || rn1 <= T(0.25) * rn2)) break;
-          step *= T(0.5);
-        }
-        T dn2 = T(0), sn2 = T(0);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const T dk = cand[k] - sc[k];
-          dn2 += dk * dk;
-          sc[k] = cand[k];
-          r[k] = r1[k];
-          sn2 += cand[k] * cand[k];
-        }
+        first = false;
         phi = phi1;
-        nit = it + 1;
-        if (dn2 <= ntol2 * fmax(sn2, T(1))) {
-          conv = true;
-          break;
+        rn2 = rn1;
+        {
+          // Newton direction in FP32: the residual, line search and stop
+          // test stay in T, so the converged stress is the T-precision root
+          float J[21], mr[6], df[6];
+          local_jacobian<float>(M, w, cj, J);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) mr[k] = -float(r[k]);
+          ldl_solve(J, mr, df);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) d[k] = T(df[k]);
         }
+        slope = T(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) slope += r[k] * d[k];
+        step = T(1);
       }
       fail = conv ? 0 : 1;
     } else {  // MODE_TANGENT: linear solve with the tangent at the given stress
-      T st[6], w[12], g6[6], visc, asum, J[21];
+      T R[9], st[6], stc[6], w[12], g6[6], visc, asum, J[21];
+      rot(R);
 #pragma unroll
       for (int k = 0; k < 6; ++k) st[k] = a.sig_t[(size_t)k * vox + g];
-      to_crystal(R, st, sc);
-      flow_eval(sc, itauc, T(M.n), M.n_int, w, g6, visc, asum);
-      local_jacobian(M, w, T(M.c1) * T(M.n) * itauc, J);
+      to_crystal(R, st, stc);
+      flow_eval<INTN>(stc, itauc, T(M.n), M.n_int, w, g6, visc, asum);
+      local_jacobian<T>(M, w, T(M.c1) * T(M.n) * itauc, J);
       ldl_solve(J, b, sc);
       nit = 1;
     }
 
     // back to the sample frame; eps = e - C0^-1 (sigma - lam); tau = sigma - C0 eps
-    T sig[6], dsl[6], err[6], tau[6];
-    to_sample(R, sc, sig);
+    T sig[6], err[6], e[6];
+    {
+      T R[9], dsl[6];
+      rot(R);
+      to_sample(R, sc, sig);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) dsl[k] = sig[k] - lam[k];
-    cubic_mul(ci_d, ci_o, ci_s, dsl, err);
-    T tr = T(0), eps[6];
+      for (int k = 0; k < 6; ++k) dsl[k] = sig[k] - a.lam[(size_t)k * vox + g];
+      cubic_mul(ci_d, ci_o, ci_s, dsl, err);
+    }
+    load_e(e);
+    T tr = T(0), eps[6], tau[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       eps[k] = e[k] - err[k];
@@ -267,7 +296,9 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs<T> a) {
     part[0] += e2;
     part[7] += se;
     part[8] += (double)fail;
-    part[9] = fmax(part[9], (double)nit);
+    part[9] += (double)nit;
+    part[10] += (double)nls;
+    part[11] = fmax(part[11], (double)nit);
   }
   __syncthreads();
   fft_lines<T, N0, false, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
@@ -300,7 +331,7 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs<T> a) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) a.e_nyq_next[(size_t)k * planes + line0 + l] = s * en[k];
   }
-  block_reduce<NPART, 1>(part, a.partial + (size_t)blockIdx.x * NPART);
+  block_reduce<NPART, 1>(part, a.partial + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,41 +454,54 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// finalize: one block
+// reduction, stop test and mixed-BC update: one block of 1024 threads
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
+__global__ __launch_bounds__(1024) void k_finalize(FinArgs a) {
   Ctl* ctl = a.ctl;
   if (ctl->done) return;
   double v[NPART];
 #pragma unroll
   for (int k = 0; k < NPART; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < a.nblocks; b += 256) {
-    const double* p = a.partial + (size_t)b * NPART;
+  const int nb = a.nblocks;
+  for (int b = threadIdx.x; b < nb; b += 1024) {
 #pragma unroll
-    for (int k = 0; k < NPART - 1; ++k) v[k] += p[k];
-    v[NPART - 1] = fmax(v[NPART - 1], p[NPART - 1]);
+    for (int k = 0; k < NPART - 1; ++k) v[k] += a.partial[(size_t)k * nb + b];
+    v[NPART - 1] = fmax(v[NPART - 1], a.partial[(size_t)(NPART - 1) * nb + b]);
   }
-  __shared__ double tot[NPART];
-  block_reduce<NPART, 1>(v, tot);
+  __shared__ double red[16][NPART];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) {
+    const double r = (k == NPART - 1) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0) red[wv][k] = r;
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
+  double tot[NPART];
+  for (int k = 0; k < NPART; ++k) {
+    double r = red[0][k];
+    for (int w = 1; w < 16; ++w) r = (k == NPART - 1) ? fmax(r, red[w][k]) : r + red[w][k];
+    tot[k] = r;
+  }
   const double iv = 1.0 / a.nvox;
-  double Sig[6], nE = 0.0, nS = 0.0, nb = 0.0, dS[6];
+  double Sig[6], nE = 0.0, nS = 0.0, nbc = 0.0, dS[6];
   for (int k = 0; k < 6; ++k) {
     Sig[k] = tot[1 + k] * iv;
     nE += ctl->E[k] * ctl->E[k];
     nS += Sig[k] * Sig[k];
     dS[k] = a.strain_ctrl[k] ? 0.0 : (a.sig_star[k] - Sig[k]);
-    nb += dS[k] * dS[k];
+    nbc += dS[k] * dS[k];
   }
   const double err_c = sqrt(tot[0] * iv) / sqrt(nE);
-  const double err_bc = nS > 0.0 ? sqrt(nb / nS) : (nb == 0.0 ? 0.0 : INFINITY);
+  const double err_bc = nS > 0.0 ? sqrt(nbc / nS) : (nbc == 0.0 ? 0.0 : INFINITY);
   for (int k = 0; k < 6; ++k) ctl->Sigma[k] = Sig[k];
   ctl->err_c = err_c;
   ctl->err_bc = err_bc;
   ctl->se = tot[7] * iv;
   ctl->nfail = tot[8];
-  ctl->nmax = tot[9];
+  ctl->nsum = tot[9];
+  ctl->lssum = tot[10];
+  ctl->nmax = tot[11];
   ctl->iters += 1;
   if (!isfinite(err_c) || isnan(err_bc) || !isfinite(nS)) {
     ctl->done = 2;
@@ -471,6 +515,11 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
       ctl->E[i] += s;
     }
   }
+}
+
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +537,8 @@ __global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
     const double rho = a.rho[g];
     const double tauc = a.m.tau0 + a.m.taylor * sqrt(rho);
     double w[12], gk[6], visc, asum;
-    flow_eval(sc, 1.0 / tauc, a.m.n, a.m.n_int, w, gk, visc, asum);
+    if (a.m.n_int > 0) flow_eval<true>(sc, 1.0 / tauc, a.m.n, a.m.n_int, w, gk, visc, asum);
+    else flow_eval<false>(sc, 1.0 / tauc, a.m.n, a.m.n_int, w, gk, visc, asum);
     double dpc[6], dp[6];
     for (int k = 0; k < 6; ++k) dpc[k] = a.gdot0 * (k < 3 ? kUN : kUS) * gk[k];
     to_sample(R, dpc, dp);
@@ -571,11 +621,14 @@ static inline int grid_for(size_t n) {
 template <typename T, int MODE>
 hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s) {
   const int planes = a.n1 * a.n2;
-#define FFTEVP_LOCAL(N)                                                         \
-  case N: {                                                                     \
-    const int lpb = LocalShape<T, N>::LPB;                                      \
-    hipLaunchKernelGGL((k_local<T, N, MODE>), dim3(planes / lpb), dim3(256), 0, s, a); \
-    break;                                                                      \
+#define FFTEVP_LOCAL(N)                                                                       \
+  case N: {                                                                                   \
+    const int lpb = LocalShape<T, N>::LPB;                                                    \
+    if (MODE == MODE_EXPORT || a.m.n_int > 0)                                                 \
+      hipLaunchKernelGGL((k_local<T, N, MODE, true>), dim3(planes / lpb), dim3(256), 0, s, a);  \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_local<T, N, MODE, false>), dim3(planes / lpb), dim3(256), 0, s, a); \
+    break;                                                                                    \
   }
   switch (n0) {
     FFTEVP_LOCAL(8)
@@ -653,11 +706,6 @@ hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s) {
     case 512: return zgamma_tx<T, 512, z_tile<T>(512)>(a, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
 }
 
 template <typename T>

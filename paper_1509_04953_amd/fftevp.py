@@ -8,7 +8,7 @@ CPU fallback: if the library or a GPU is missing, construction raises.
 from __future__ import annotations
 
 import ctypes as C
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from pathlib import Path
 
 import numpy as np
@@ -45,7 +45,8 @@ class OptsC(C.Structure):
 class ReportC(C.Structure):
     _fields_ = [("iters", C.c_int), ("newton_max_seen", C.c_int), ("newton_failed", C.c_int),
                 ("err_c", C.c_double), ("err_bc", C.c_double), ("Sigma", C.c_double * 6),
-                ("E", C.c_double * 6), ("rho_mean", C.c_double)]
+                ("E", C.c_double * 6), ("rho_mean", C.c_double),
+                ("newton_mean", C.c_double), ("linesearch_mean", C.c_double)]
 
 
 def library():
@@ -135,7 +136,8 @@ class Report:
     Sigma: np.ndarray
     E: np.ndarray
     rho_mean: float
-    extra: dict = field(default_factory=dict)
+    newton_mean: float = 0.0
+    linesearch_mean: float = 0.0
 
 
 def _opts(o: Opts | None):
@@ -204,7 +206,8 @@ class Solver:
         r = ReportC()
         st = self._check(self.lib.fftevp_step(self.h, C.byref(_opts(opts)), C.byref(r)), allow)
         return Report(st, r.iters, r.newton_max_seen, r.newton_failed, r.err_c, r.err_bc,
-                      np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean)
+                      np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean, r.newton_mean,
+                      r.linesearch_mean)
 
     def field(self, name: str):
         n = NCOMP[name]
