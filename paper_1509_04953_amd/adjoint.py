@@ -1,0 +1,105 @@
+"""Gradients of a volume-averaged stress-strain curve (reverse mode).
+
+``StressStrainCurve.apply(theta, problem)`` runs the increments of a loading
+path on the GPU and returns the curve <sigma33>_t, t = 1..T, as a tensor; its
+backward pass gives d(loss)/d(theta) for theta = (tau0, k1, k2, n) through
+the library's adjoint of each converged increment (implicit differentiation
+of the fixed point, one linear tangent solve per increment).
+
+Memory: the forward keeps a state snapshot every ``checkpoint_every``
+increments (default ~sqrt(T)); the backward recomputes one segment at a time
+from its checkpoint, keeping that segment's snapshots, then walks it in
+reverse. Recomputation is bit-identical because every kernel is
+deterministic.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+
+import numpy as np
+import torch
+
+from .fftevp import Load, Material, Opts, Solver, OK
+
+
+@dataclass
+class CurveProblem:
+    solver: Solver
+    material: Material
+    quat: object
+    rho: object
+    load: Load
+    increments: int
+    opts: Opts = None
+    adjoint_opts: Opts = None
+    checkpoint_every: int = 0
+
+
+def _material(base: Material, theta) -> Material:
+    th = [float(x) for x in theta]
+    return replace(base, tau0=th[0], k1=th[1], k2=th[2], n=th[3])
+
+
+def _forward(p: CurveProblem, theta, keep_every):
+    s = p.solver
+    s.set_material(_material(p.material, theta))
+    s.set_microstructure(p.quat, p.rho)
+    s.set_loading(p.load)
+    ckpts = {0: s.save_state()}
+    curve = []
+    for t in range(1, p.increments + 1):
+        r = s.step(p.opts)
+        if r.status != OK:
+            raise RuntimeError(f"increment {t} did not converge (status {r.status})")
+        curve.append(r.Sigma[2])
+        if keep_every and t % keep_every == 0 and t < p.increments:
+            ckpts[t] = s.save_state()
+    return np.array(curve), ckpts
+
+
+def curve(p: CurveProblem, theta):
+    """<sigma33>_t for t = 1..T (no gradient bookkeeping)."""
+    c, _ = _forward(p, theta, 0)
+    return c
+
+
+class StressStrainCurve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, p: CurveProblem):
+        T = p.increments
+        every = p.checkpoint_every or max(1, int(math.ceil(math.sqrt(T))))
+        c, ckpts = _forward(p, theta.detach().cpu().numpy(), every)
+        ctx.p, ctx.every, ctx.ckpts = p, every, ckpts
+        ctx.theta = theta.detach().cpu().numpy()
+        return torch.as_tensor(c, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad):
+        p, every, ckpts = ctx.p, ctx.every, ctx.ckpts
+        s = p.solver
+        g = grad.detach().cpu().numpy().astype(np.float64)
+        T = p.increments
+        adj = torch.zeros(s.adjoint_bytes(), dtype=torch.uint8, device="cuda")
+        dth = np.zeros(4)
+        starts = sorted(ckpts)
+        for a in reversed(starts):
+            b = min(a + every, T)
+            s.load_state(ckpts[a])
+            states = [ckpts[a]]
+            for _ in range(a + 1, b + 1):
+                r = s.step(p.opts)
+                if r.status != OK:
+                    raise RuntimeError("recomputation did not converge")
+                states.append(s.save_state())
+            for t in range(b, a, -1):
+                dS = (0.0, 0.0, float(g[t - 1]), 0.0, 0.0, 0.0)
+                dth = s.adjoint_increment(states[t - 1 - a], states[t - a], dS, adj, dth,
+                                          p.adjoint_opts or p.opts)
+            del states
+        return torch.as_tensor(dth, dtype=grad.dtype), None
+
+
+def curve_loss(c, target):
+    """L = (1/T) sum_t (<sigma33>_t - target_t)^2 (MPa^2)."""
+    return torch.mean((c - target) ** 2)

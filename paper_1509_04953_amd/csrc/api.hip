@@ -42,6 +42,7 @@ struct fftevp_ctx {
   size_t tsize = 8;
   hipStream_t stream = nullptr;
   bool have_mat = false, have_micro = false, have_load = false;
+  bool state_ok = false;  // false after an adjoint solve reused the state buffers
   fftevp_cubic cubic{};
   fftevp_flow flow{};
   fftevp_loading load{};
@@ -59,6 +60,7 @@ struct fftevp_ctx {
   double t = 0.0;
   double inc = 0.0;
   int last_iters = 0;
+  int adj_iters = 0;
   std::string err;
   // kernel timing
   bool prof = false;
@@ -252,12 +254,12 @@ fftevp_status alloc_all(fftevp_ctx* ctx) {
   }
   ctx->local_nb = local_blocks<T>(ctx->n0, ctx->n1, ctx->n2);
   ctx->red_nb = 1024;
-  const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 2);
+  const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->partial, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->ctl, sizeof(Ctl));
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc((void**)&ctx->red2, 2 * sizeof(double));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->red2_h, 2 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&ctx->red2, 8 * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->red2_h, 8 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e == hipErrorOutOfMemory) return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
   if (e != hipSuccess) return fail(ctx, FFTEVP_EHIP, std::string("allocation: ") + hipGetErrorString(e));
@@ -504,6 +506,100 @@ size_t snap_layout(const fftevp_ctx* c, size_t off[6]) {
   return o;
 }
 
+// Header check of a snapshot against this context.
+fftevp_status check_snapshot(fftevp_ctx* ctx, const void* snap) {
+  double hdr[kHeader];
+  HIPCHK(hipMemcpyAsync(hdr, snap, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
+      hdr[4] != ctx->n2)
+    return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
+  return FFTEVP_OK;
+}
+
+// Adjoint of one increment. With a_eps = dL/d epsp_t and a_rho = dL/d rho_t
+// (sums over voxels), the linearised increment maps a perturbation of the
+// local eigenstrain to the stress through the heterogeneous tangent problem;
+// its transpose is the same problem with eigenstrain eta and mean strain
+// -g/N^3 on the strain-controlled components, solved with the spectral
+// iteration in tangent mode. A per-voxel reverse update then carries the
+// adjoints back to the start of the increment and accumulates dL/dtheta.
+template <typename T>
+fftevp_status adjoint_impl(fftevp_ctx* ctx, const fftevp_opts& o, const void* before, const void* after,
+                           const double* g, void* adj, double* dth) {
+  fftevp_status st = check_snapshot(ctx, before);
+  if (st != FFTEVP_OK) return st;
+  if ((st = check_snapshot(ctx, after)) != FFTEVP_OK) return st;
+  const size_t V = ctx->V, ts = sizeof(T);
+  size_t off[6];
+  snap_layout(ctx, off);
+  if (!ctx->b.a_eta) HIPCHK(hipMalloc(&ctx->b.a_eta, 6 * V * ts));
+  AdjArgs<T> aa{};
+  aa.sig_t = (const T*)((const char*)after + off[2]);
+  aa.rho0 = (const T*)((const char*)before + off[1]);
+  aa.quat = (const T*)ctx->b.quat;
+  aa.a_eps = (T*)adj;
+  aa.a_rho = (T*)adj + 6 * V;
+  aa.eta = (T*)ctx->b.a_eta;
+  aa.partial = ctx->partial;
+  aa.nvox = V;
+  aa.b.dt = ctx->load.dt;
+  aa.b.gdot0 = ctx->flow.gdot0;
+  aa.b.n = ctx->flow.n;
+  aa.b.tau0 = ctx->flow.tau0;
+  aa.b.taylor = ctx->flow.alpha * ctx->flow.mu * ctx->flow.b;
+  aa.b.k1 = ctx->flow.k1;
+  aa.b.k2 = ctx->flow.k2;
+  const double nf = std::floor(aa.b.n);
+  aa.b.n_int = (nf == aa.b.n && aa.b.n >= 1.0 && aa.b.n <= 64.0) ? (int)aa.b.n : 0;
+  // 1. eigenstrain of the adjoint problem
+  HIPCHK(timed(ctx, 6, -1, [&] { return launch_adj_setup<T>(aa, ctx->red_nb, ctx->red2, ctx->stream); }));
+  HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const double eta_rms = std::sqrt(ctx->red2_h[0] / (double)V);
+  // 2. tangent solve from zero fields; the forward state buffers are reused
+  ctx->state_ok = false;
+  HIPCHK(hipMemsetAsync(ctx->b.emain[ctx->ec], 0, 6 * V * ts, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->b.enyq[ctx->ec], 0, 6 * ctx->planes * ts, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->b.sig[ctx->sc], 0, 6 * V * ts, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->b.sig[ctx->sw], 0, 6 * V * ts, ctx->stream));
+  double E0[6], gm[6], En = 0.0;
+  to_mandel(g, gm);
+  for (int k = 0; k < 6; ++k) {
+    // dL/d<sigma>_plain . d<sigma>_plain = (g_k / w_k) d<sigma>_Mandel,k
+    const double wk = k < 3 ? 1.0 : kR2;
+    E0[k] = ctx->load.strain_ctrl[k] ? -(g[k] / wk) / (double)V : 0.0;
+    En += E0[k] * E0[k];
+  }
+  (void)gm;
+  En = std::sqrt(En);
+  if (En > 0.0 || eta_rms > 0.0) {
+    const C0 c0 = reference_medium(ctx, &o);
+    const Mat m = make_mat(ctx, c0, ctx->load.dt, 1e-12, o.newton_max);
+    FinArgs fin = make_fin(ctx, o, c0);
+    for (int k = 0; k < 6; ++k) fin.sig_star[k] = 0.0;
+    fin.enorm = std::max(En, eta_rms);
+    SolveOut so;
+    const int keep = ctx->last_iters;
+    ctx->last_iters = ctx->adj_iters;
+    st = solve_loop<T, MODE_TANGENT>(ctx, o, m, c0, fin, E0, E0, ctx->b.sig[ctx->sc], ctx->b.a_eta, aa.rho0,
+                                     aa.sig_t, so);
+    ctx->adj_iters = so.iters;
+    ctx->last_iters = keep;
+    if (st != FFTEVP_OK) return st;
+    if (so.done == 2) return fail(ctx, FFTEVP_ENONFINITE, "adjoint solve: non-finite residual");
+    if (so.done != 1) return fail(ctx, FFTEVP_NOT_CONVERGED, "adjoint solve: max_iter reached");
+  }
+  // 3. reverse update; z is the working stress (zero when the problem is trivial)
+  aa.z = (const T*)ctx->b.sig[ctx->sw];
+  HIPCHK(timed(ctx, 6, -1, [&] { return launch_adj_update<T>(aa, ctx->red_nb, ctx->red2, ctx->stream); }));
+  HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->prof) HIPCHK(harvest(ctx, 0, false));
+  for (int k = 0; k < 4; ++k) dth[k] += ctx->red2_h[k];
+  return FFTEVP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -611,6 +707,7 @@ fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat, con
   ctx->sw = 1;
   ctx->last_iters = 0;
   ctx->have_micro = true;
+  ctx->state_ok = true;
   return FFTEVP_OK;
 }
 
@@ -635,6 +732,8 @@ fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_repor
   if (!ctx) return FFTEVP_EINVAL;
   if (!ctx->have_mat || !ctx->have_micro || !ctx->have_load)
     return fail(ctx, FFTEVP_ESTATE, "set_material, set_microstructure and set_loading must come first");
+  if (!ctx->state_ok)
+    return fail(ctx, FFTEVP_ESTATE, "an adjoint solve reused the state buffers: load a snapshot first");
   if (opts && (!(opts->tol >= 0.0) || opts->c0_mu < 0.0 || (opts->c0_mu > 0.0 && !(opts->c0_lambda + 2.0 * opts->c0_mu / 3.0 > 0.0))))
     return fail(ctx, FFTEVP_EINVAL, "bad options");
   const fftevp_opts o = resolve_opts(ctx, opts);
@@ -744,6 +843,7 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   ctx->inc = hdr[12];
   ctx->last_iters = (int)hdr[13];
   ctx->e_last = ctx->ec;
+  ctx->state_ok = true;
   return FFTEVP_OK;
 }
 
@@ -771,9 +871,16 @@ size_t fftevp_adjoint_bytes(const fftevp_ctx* ctx) {
   return 7 * ctx->V * ctx->tsize;
 }
 
-fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts*, const void*, const void*,
-                                       const double*, void*, double*) {
-  return fail(ctx, FFTEVP_ESTATE, "adjoint not available");
+fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts, const void* before,
+                                       const void* after, const double* g, void* adj, double* dth) {
+  if (!ctx || !before || !after || !g || !adj || !dth) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (!ctx->have_mat || !ctx->have_micro || !ctx->have_load)
+    return fail(ctx, FFTEVP_ESTATE, "set_material, set_microstructure and set_loading must come first");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(g[k])) return fail(ctx, FFTEVP_EINVAL, "non-finite dL/dSigma");
+  const fftevp_opts o = resolve_opts(ctx, opts);
+  return ctx->prec == FFTEVP_FP64 ? adjoint_impl<double>(ctx, o, before, after, g, adj, dth)
+                                  : adjoint_impl<float>(ctx, o, before, after, g, adj, dth);
 }
 
 }  // extern "C"

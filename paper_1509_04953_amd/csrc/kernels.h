@@ -29,6 +29,7 @@ struct FinArgs {
   const double* partial;  // [NPART][blocks]
   int nblocks;
   double nvox, tol;
+  double enorm;        // > 0: normalises err_c instead of |E|
   int strain_ctrl[6];
   double sig_star[6];  // Mandel
   double css[36];      // [(C0)_ss]^-1 embedded in 6x6 (Mandel), zero elsewhere
@@ -88,6 +89,26 @@ struct StateArgs {
   Mat m;
 };
 
+// scalar parameters of the adjoint kernels
+struct AdjArgsBase {
+  double dt, gdot0, n, tau0, taylor, k1, k2;
+  int n_int;
+};
+
+template <typename T>
+struct AdjArgs {
+  const T* sig_t;   // converged stress of the increment, [6][V] Mandel
+  const T* rho0;    // density at the start of the increment, [V]
+  const T* quat;
+  T* a_eps;         // adjoint of the plastic strain (in/out), [6][V] Mandel
+  T* a_rho;         // adjoint of the density (in/out), [V]
+  T* eta;           // out (setup): eigenstrain of the adjoint linear problem
+  const T* z;       // in (update): stress solving the adjoint linear problem
+  double* partial;
+  size_t nvox;
+  AdjArgsBase b;
+};
+
 struct Shift6 {
   double v[6];
 };
@@ -112,5 +133,9 @@ template <typename T>
 hipError_t launch_shift_dc(cx<T>* main, size_t planes, int h, const double dE[6], hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_setup(const AdjArgs<T>& a, int nblocks, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_update(const AdjArgs<T>& a, int nblocks, double* out, hipStream_t s);
 
 }  // namespace fftevp

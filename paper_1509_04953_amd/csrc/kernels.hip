@@ -492,7 +492,7 @@ __global__ __launch_bounds__(1024) void k_finalize(FinArgs a) {
     dS[k] = a.strain_ctrl[k] ? 0.0 : (a.sig_star[k] - Sig[k]);
     nbc += dS[k] * dS[k];
   }
-  const double err_c = sqrt(tot[0] * iv) / sqrt(nE);
+  const double err_c = sqrt(tot[0] * iv) / (a.enorm > 0.0 ? a.enorm : sqrt(nE));
   const double err_bc = nS > 0.0 ? sqrt(nbc / nS) : (nbc == 0.0 ? 0.0 : INFINITY);
   for (int k = 0; k < 6; ++k) ctl->Sigma[k] = Sig[k];
   ctl->err_c = err_c;
@@ -558,6 +558,150 @@ __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ p, int 
     v[1] += p[2 * b + 1];
   }
   block_reduce<2, 0>(v, out);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of one increment (reverse mode through the converged fixed point)
+// ---------------------------------------------------------------------------
+// Flow quantities at a stress, crystal frame, FP64: x_a, |x_a|^n, |x_a|^(n-1).
+__device__ __forceinline__ void adj_flow(const AdjArgsBase& a, const double (&sc)[6], double itauc,
+                                         double (&x)[12], double (&p)[12], double (&w)[12]) {
+  static_for<0, 12>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    x[A] = resolved<A>(sc) * itauc;
+  });
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const double ax = fabs(x[q]);
+    double wq;
+    if (a.n_int > 0) {
+      wq = 1.0;
+      double bq = ax;
+      for (int e = a.n_int - 1; e != 0; e >>= 1) {
+        if (e & 1) wq *= bq;
+        bq *= bq;
+      }
+    } else {
+      wq = ax > 0.0 ? exp((a.n - 1.0) * log(ax)) : (a.n == 1.0 ? 1.0 : 0.0);
+    }
+    w[q] = wq;
+    p[q] = wq * ax;
+  }
+}
+
+template <int A>
+__device__ __forceinline__ void add_schmid(double (&v)[6], double c) {
+  static_for<0, 6>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    acc_sign<kSign[A][K]>(v[K], c * (K < 3 ? kUN : kUS));
+  });
+}
+
+// eigenstrain of the adjoint linear problem:
+//   eta = dt [ sum_a gdot'_a m_a (m_a : a_eps) + a_rho h sum_a sign(tau_a) gdot'_a m_a ]
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_setup(AdjArgs<T> a) {
+  const size_t V = a.nvox;
+  double part[1] = {0.0};
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double R[9], s[6], sc[6], ae[6], aec[6];
+    quat_rot<double>(a.quat[g], a.quat[V + g], a.quat[2 * V + g], a.quat[3 * V + g], R);
+    for (int k = 0; k < 6; ++k) {
+      s[k] = a.sig_t[k * V + g];
+      ae[k] = a.a_eps[k * V + g];
+    }
+    to_crystal(R, s, sc);
+    to_crystal(R, ae, aec);
+    const double rho = a.rho0[g], sr = sqrt(rho);
+    const double tauc = a.b.tau0 + a.b.taylor * sr;
+    const double h = a.b.k1 * sr - a.b.k2 * rho;
+    const double arho = a.a_rho[g];
+    double x[12], p[12], w[12];
+    adj_flow(a.b, sc, 1.0 / tauc, x, p, w);
+    double ec[6] = {0, 0, 0, 0, 0, 0};
+    const double gd1 = a.b.gdot0 * a.b.n / tauc;  // dgdot/dtau = gd1 |x|^(n-1)
+    static_for<0, 12>([&](auto ac) {
+      constexpr int A = decltype(ac)::value;
+      const double ma = resolved<A>(aec);
+      const double sg = x[A] < 0.0 ? -1.0 : (x[A] > 0.0 ? 1.0 : 0.0);
+      add_schmid<A>(ec, a.b.dt * gd1 * w[A] * (ma + arho * h * sg));
+    });
+    double es[6];
+    to_sample(R, ec, es);
+    double n2 = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      a.eta[k * V + g] = (T)es[k];
+      n2 += es[k] * es[k];
+    }
+    part[0] += n2;
+  }
+  block_reduce<1, 0>(part, a.partial + blockIdx.x);
+}
+
+// reverse update of the state adjoints and the parameter-gradient partials
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_update(AdjArgs<T> a) {
+  const size_t V = a.nvox;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};  // d/d tau0, k1, k2, n
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double R[9], s[6], sc[6], at[6], atc[6];
+    quat_rot<double>(a.quat[g], a.quat[V + g], a.quat[2 * V + g], a.quat[3 * V + g], R);
+    for (int k = 0; k < 6; ++k) {
+      s[k] = a.sig_t[k * V + g];
+      at[k] = (double)a.a_eps[k * V + g] + (double)a.z[k * V + g];
+    }
+    to_crystal(R, s, sc);
+    to_crystal(R, at, atc);
+    const double rho = a.rho0[g], sr = sqrt(rho);
+    const double tauc = a.b.tau0 + a.b.taylor * sr;
+    const double h = a.b.k1 * sr - a.b.k2 * rho;
+    const double hp = a.b.k1 / (2.0 * sr) - a.b.k2;
+    const double arho = a.a_rho[g];
+    double x[12], p[12], w[12];
+    adj_flow(a.b, sc, 1.0 / tauc, x, p, w);
+    double A1 = 0.0, gam = 0.0, dn1 = 0.0, dn2 = 0.0;
+    static_for<0, 12>([&](auto ac) {
+      constexpr int A = decltype(ac)::value;
+      const double gdot = a.b.gdot0 * (x[A] < 0.0 ? -p[A] : p[A]);
+      const double ma = resolved<A>(atc);
+      const double lx = p[A] > 0.0 ? log(fabs(x[A])) : 0.0;
+      A1 += ma * gdot;
+      gam += fabs(gdot);
+      dn1 += ma * gdot * lx;
+      dn2 += fabs(gdot) * lx;
+    });
+    const double dt = a.b.dt;
+    const double atau = -dt * (a.b.n / tauc) * (A1 + arho * h * gam);
+    part[0] += atau;
+    part[1] += arho * dt * sr * gam;
+    part[2] -= arho * dt * rho * gam;
+    part[3] += dt * (dn1 + arho * h * dn2);
+    a.a_rho[g] = (T)(arho * (1.0 + dt * hp * gam) + atau * a.b.taylor / (2.0 * sr));
+    for (int k = 0; k < 6; ++k) a.a_eps[k * V + g] = (T)at[k];
+  }
+  block_reduce<4, 0>(part, a.partial + blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ p, int n, int rows,
+                                                  double* out) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < n; b += 256)
+    for (int r = 0; r < rows; ++r) v[r] += p[(size_t)r * n + b];
+  block_reduce<4, 0>(v, out);
+}
+
+template <typename T>
+hipError_t launch_adj_setup(const AdjArgs<T>& a, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_setup<T>, dim3(nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, (const double*)a.partial, nblocks, 1, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_update(const AdjArgs<T>& a, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_update<T>, dim3(nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, (const double*)a.partial, nblocks, 4, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -756,7 +900,9 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
                                        double*, hipStream_t);                                  \
   template hipError_t launch_export<T>(const T*, double*, size_t, int, int, hipStream_t);      \
   template hipError_t launch_shift_dc<T>(cx<T>*, size_t, int, const double*, hipStream_t);     \
-  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);
+  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                              \
+  template hipError_t launch_adj_setup<T>(const AdjArgs<T>&, int, double*, hipStream_t);        \
+  template hipError_t launch_adj_update<T>(const AdjArgs<T>&, int, double*, hipStream_t);
 
 FFTEVP_INST(double)
 FFTEVP_INST(float)

@@ -1,0 +1,56 @@
+"""Write the stored expected values of the GPU tests. Calls only the oracle.
+
+    python tests/golden/make_golden.py
+
+* adjoint_8cube.json: an 8^3 four-grain polycrystal; the mean-stress curve
+  over 3 compression increments at the reference parameters, the target
+  curve at perturbed parameters theta* = theta0 * (1.05, 0.95, 1.05, 0.95),
+  and the central finite-difference gradient of the curve loss
+  L = mean_t (<s33>_t - target_t)^2 with respect to (tau0, k1, k2, n).
+* curve_16cube.json: the mean-stress curve of the 16^3 eight-grain
+  polycrystal (uniform density) over 5 increments.
+Both solve each increment to a stop tolerance of 1e-13.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import Flow, Loading, stress_curve, fd_gradient, curve_loss  # noqa: E402
+
+
+def adjoint_case():
+    w = synth.Workload("adj8", (8, 8, 8), 4, "lognormal", 3, 1e-13, seed=41)
+    q, rho, _ = synth.make_microstructure(w)
+    f0 = Flow()
+    th0 = f0.theta()
+    ths = th0 * np.array([1.05, 0.95, 1.05, 0.95])
+    load = Loading()
+    c0, r0 = stress_curve(w.shape, q, rho, f0, load, w.increments, tol=1e-13)
+    cs, _ = stress_curve(w.shape, q, rho, f0.with_theta(ths), load, w.increments, tol=1e-13)
+    g = fd_gradient(w.shape, q, rho, f0, load, w.increments, cs, rel_step=1e-5, tol=1e-13)
+    return {"workload": {"shape": w.shape, "grains": w.n_grains, "rho": w.rho, "seed": w.seed},
+            "theta0": th0.tolist(), "theta_star": ths.tolist(), "increments": w.increments,
+            "curve_theta0": c0.tolist(), "target": cs.tolist(), "loss": curve_loss(c0, cs),
+            "fd_gradient": g.tolist(), "fd_rel_step": 1e-5, "tol": 1e-13,
+            "iters": [r["iters"] for r in r0]}
+
+
+def curve16():
+    w = synth.workload("cu16")
+    q, rho, _ = synth.make_microstructure(w)
+    c, reps = stress_curve(w.shape, q, rho, Flow(), Loading(), w.increments, tol=1e-13)
+    return {"workload": "cu16", "curve": c.tolist(), "iters": [r["iters"] for r in reps],
+            "E33": [r["E"][2] for r in reps], "tol": 1e-13}
+
+
+if __name__ == "__main__":
+    with open(os.path.join(HERE, "adjoint_8cube.json"), "w") as fh:
+        json.dump(adjoint_case(), fh, indent=1)
+    with open(os.path.join(HERE, "curve_16cube.json"), "w") as fh:
+        json.dump(curve16(), fh, indent=1)

@@ -1,0 +1,81 @@
+"""Adjoint gradients of the stress-strain curve loss (GPU, through the C ABI).
+
+Checks d L / d(tau0, k1, k2, n), L = mean_t (<s33>_t - target_t)^2, against
+(1) central finite differences of the GPU forward (relative 1e-6 per
+component), (2) the oracle's central finite differences stored in
+tests/golden/adjoint_8cube.json (relative 1e-5), and checks that the
+checkpoint schedule does not change the gradient.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "adjoint_8cube.json")
+
+
+def problem(every=0, precision="fp64", tol=1e-13):
+    import torch  # noqa: F401
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    from paper_1509_04953_amd.adjoint import CurveProblem
+    d = json.load(open(GOLD))
+    w = d["workload"]
+    wl = synth.Workload("adj8", tuple(w["shape"]), w["grains"], w["rho"], d["increments"], tol,
+                        seed=w["seed"])
+    q, rho, _ = synth.make_microstructure(wl)
+    s = Solver(wl.shape, precision)
+    opts = Opts(tol=tol, max_iter=5000)
+    return d, CurveProblem(s, Material(), q.reshape(4, -1), rho.reshape(-1), Load(),
+                           d["increments"], opts, opts, every)
+
+
+def adjoint_grad(p, theta0, target):
+    import torch
+    from paper_1509_04953_amd.adjoint import StressStrainCurve, curve_loss
+    th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    c = StressStrainCurve.apply(th, p)
+    L = curve_loss(c, torch.tensor(target, dtype=torch.float64))
+    L.backward()
+    return c.detach().numpy(), float(L), th.grad.numpy().copy()
+
+
+def test_adjoint_against_finite_differences(require_gpu):
+    from paper_1509_04953_amd.adjoint import curve
+    d, p = problem()
+    th0 = np.array(d["theta0"])
+    tgt = np.array(d["target"])
+    print("case: adjoint 8^3, 3 increments", flush=True)
+    c, L, g = adjoint_grad(p, th0, tgt)
+    # forward agrees with the oracle's curve
+    assert np.abs(c - np.array(d["curve_theta0"])).max() < 1e-10 * np.abs(c).max()
+    assert abs(L - d["loss"]) < 1e-9 * d["loss"]
+    fd = np.zeros(4)
+    for k in range(4):
+        h = 1e-5 * abs(th0[k])
+        tp, tm = th0.copy(), th0.copy()
+        tp[k] += h
+        tm[k] -= h
+        Lp = np.mean((curve(p, tp) - tgt) ** 2)
+        Lm = np.mean((curve(p, tm) - tgt) ** 2)
+        fd[k] = (Lp - Lm) / (2 * h)
+    print("adjoint", g, "\nfd     ", fd, "\noracle ", d["fd_gradient"], flush=True)
+    rel = np.abs(g - fd) / np.abs(fd)
+    assert rel.max() < 1e-6, rel
+    relo = np.abs(g - np.array(d["fd_gradient"])) / np.abs(np.array(d["fd_gradient"]))
+    assert relo.max() < 1e-5, relo
+
+
+def test_checkpoint_schedule_is_exact(require_gpu):
+    d, p1 = problem(every=1)
+    _, p3 = problem(every=3)
+    th0 = np.array(d["theta0"])
+    tgt = np.array(d["target"])
+    print("case: checkpoint schedules 1 and 3", flush=True)
+    _, _, g1 = adjoint_grad(p1, th0, tgt)
+    _, _, g3 = adjoint_grad(p3, th0, tgt)
+    assert np.array_equal(g1, g3), (g1, g3)

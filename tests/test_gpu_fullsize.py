@@ -1,0 +1,140 @@
+"""Full-size checks (128^3, 500 grains: the benchmark workload and launch
+configuration) and the mixed-precision path against the FP64 oracle.
+
+At full size the oracle cannot run whole increments in test time, so the
+GPU result is checked on sampled voxels (oracle material and flow rule,
+one voxel at a time) and by properties that hold at any size.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle, Loading
+from oracle import local as L
+from oracle.crystal import voxel_material
+from oracle.green import frequencies
+from oracle.tensors import voigt_to_mandel, mandel_to_tensor
+
+pytestmark = pytest.mark.gpu
+
+
+def make(w, precision):
+    from paper_1509_04953_amd import Solver, Material, Load
+    q, rho, _ = synth.make_microstructure(w)
+    q = q.reshape(4, -1)
+    rho = rho.reshape(-1)
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(q, rho)
+    s.set_loading(Load(dt=w.dt))
+    return s, q, rho
+
+
+def test_fullsize_128_properties(require_gpu):
+    from paper_1509_04953_amd import Opts
+    w = synth.workload("cu128")
+    s, q, rho0 = make(w, "fp64")
+    opts = Opts(tol=w.tol)
+    print("case: 128^3 fp64 increment 1", flush=True)
+    r1 = s.step(opts)
+    assert r1.status == 0
+    rho_prev = s.field("rho").cpu().numpy()
+    print("case: 128^3 fp64 increment 2", flush=True)
+    r2 = s.step(opts)
+    assert r2.status == 0 and r2.newton_failed == 0
+    sig = s.field("sigma").cpu().numpy()
+    e = s.field("strain").cpu().numpy()
+    ep = s.field("epsp").cpu().numpy()
+    rho = s.field("rho").cpu().numpy()
+    V = w.voxels
+    # mean strain equals the macroscopic strain; prescribed component exact
+    assert np.allclose(e.mean(axis=1), r2.E, rtol=0, atol=1e-13)
+    assert abs(r2.E[2] + 2 * w.d_eps) < 1e-15
+    # stress-free lateral means and the reported mean stress
+    S = sig.mean(axis=1)
+    assert np.allclose(S, r2.Sigma, rtol=1e-12, atol=1e-9)
+    assert np.abs(S[[0, 1, 3, 4, 5]]).max() < 10 * w.tol * abs(S[2])
+    # equilibrium in Fourier space (non-Nyquist), relative to the mean stress
+    sm = voigt_to_mandel(sig).reshape(6, 128, 128, 128)
+    sh = np.fft.rfftn(sm, axes=(1, 2, 3))
+    kx, ky, kz = frequencies(w.shape)
+    kxr = np.arange(65)
+    KZ, KY, KX = np.meshgrid(kz, ky, kxr, indexing="ij")
+    nyq = (KX == 64) | (np.abs(KY) == 64) | (np.abs(KZ) == 64)
+    T = mandel_to_tensor(np.moveaxis(sh, 0, -1))
+    div = np.einsum("zyxij,zyxj->zyxi", T, np.stack([KX, KY, KZ], -1))
+    xi = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    err_eq = np.sqrt(np.sum(np.abs(div[~nyq]) ** 2 / np.maximum(xi[~nyq], 1)[:, None] ** 2))
+    print("equilibrium residual", err_eq / np.abs(sh[:, 0, 0, 0]).max(), flush=True)
+    assert err_eq / np.abs(sh[:, 0, 0, 0]).max() < 1e-3
+    # local law at sampled voxels: e = S:sigma + epsp_t at convergence
+    rng = np.random.default_rng(0)
+    idx = rng.choice(V, 256, replace=False)
+    _, Sv, m = voxel_material(q[:, idx], 168400.0, 121400.0, 75400.0)
+    sg = voigt_to_mandel(sig[:, idx]).T
+    resid = voigt_to_mandel(e[:, idx]).T - (np.einsum("mkl,ml->mk", Sv, sg) + voigt_to_mandel(ep[:, idx]).T)
+    assert np.abs(resid).max() < 50 * w.tol * np.linalg.norm(voigt_to_mandel(r2.E))
+    # density update at sampled voxels from the converged stress
+    tauc = 5.0 + 0.5 * 47337.0 * 2.56e-10 * np.sqrt(rho_prev[idx])
+    _, gd = L.slip_rates(sg, m, tauc, 1e-3, 10.0)
+    want = rho_prev[idx] + w.dt * (8e7 * np.sqrt(rho_prev[idx]) - 10.0 * rho_prev[idx]) * np.abs(gd).sum(axis=1)
+    assert np.abs(rho[idx] - want).max() < 1e-12 * want.max()
+
+
+def test_mixed_precision_errors_vs_oracle(require_gpu):
+    """Per-field relative L2 error of the mixed path against the FP64 oracle.
+
+    Both run the same iteration with the same stop rule (tol 1e-6), so the
+    difference is the FP32 rounding of fields, transforms and Newton solves.
+    Plastic strain and density follow the slip rates, |tau|^n with n = 10, so
+    their errors are about n times the stress error.
+    """
+    from paper_1509_04953_amd import Opts
+    w = synth.workload("cu16")
+    s, q, rho = make(w, "mixed")
+    s64, _, _ = make(w, "fp64")
+    o = Oracle(w.shape, q, rho)
+    errs, errs64 = {}, {}
+    curve_g, curve_64, curve_o = [], [], []
+    for inc in range(3):
+        print(f"case: mixed 16^3 increment {inc}", flush=True)
+        r = s.step(Opts(tol=1e-6))
+        r64 = s64.step(Opts(tol=1e-6))
+        ro = o.increment(Loading(), tol=1e-6, max_iter=3000)
+        assert r64.iters == ro["iters"]
+        curve_g.append(r.Sigma[2])
+        curve_64.append(r64.Sigma[2])
+        curve_o.append(ro["Sigma"][2])
+    for k in ("sigma", "strain", "epsp", "rho"):
+        v = o.field(k)
+        errs[k] = float(np.linalg.norm(s.field(k).cpu().numpy() - v) / np.linalg.norm(v))
+        errs64[k] = float(np.linalg.norm(s64.field(k).cpu().numpy() - v) / np.linalg.norm(v))
+    co = np.array(curve_o)
+    errs["curve"] = float(np.abs(np.array(curve_g) - co).max() / np.abs(co).max())
+    errs64["curve"] = float(np.abs(np.array(curve_64) - co).max() / np.abs(co).max())
+    print("mixed-precision relative errors:", json.dumps(errs), flush=True)
+    print("fp64 relative errors:", json.dumps(errs64), flush=True)
+    for k, v in errs64.items():
+        assert v < 1e-10, (k, v)
+    assert errs["curve"] < 1e-5
+    assert errs["sigma"] < 1e-5
+    assert errs["strain"] < 1e-5
+    assert errs["epsp"] < 1e-4
+    assert errs["rho"] < 1e-4
+
+
+def test_curve_16cube_matches_golden(require_gpu):
+    from paper_1509_04953_amd import Opts
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "curve_16cube.json")))
+    w = synth.workload("cu16")
+    s, _, _ = make(w, "fp64")
+    c = []
+    for inc in range(w.increments):
+        r = s.step(Opts(tol=1e-13, max_iter=5000))
+        assert r.status == 0
+        c.append(r.Sigma[2])
+    c = np.array(c)
+    assert np.abs(c - np.array(d["curve"])).max() < 1e-10 * np.abs(c).max()
