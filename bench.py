@@ -10,7 +10,10 @@ reduction and stop test, y/z FFTs with the Green operator) and the
 end-of-increment state update. W untimed increments come first, then K timed
 ones. The FP64 path gives ``value``; the mixed-precision path (FP32 fields,
 transforms and Newton; FP64 reductions and macroscopic update) is timed the
-same way and reported under ``mixed``.
+same way and reported under ``mixed``. ``adjoint`` reports the wall time of
+the curve-loss gradient (backward, with segment recomputation from sqrt(T)
+checkpoints) over that of the forward pass, on the 128^3 / 300-grain /
+40-increment workload.
 
 voxel-iterations/s = sum over timed increments of (fixed-point iterations x
 voxels) / wall time, with inputs resident in HBM. Per-kernel durations come
@@ -76,6 +79,67 @@ def run_gpu(w, quat, rho, precision, steps, warmup):
                 rate=sum(iters) * w.voxels / dt, ms_per_step=1e3 * dt / steps)
 
 
+def run_adjoint(w, quat, rho, precision):
+    """Forward and backward wall time of the curve-loss gradient."""
+    import torch
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    from paper_1509_04953_amd.adjoint import CurveProblem, StressStrainCurve, curve_loss
+    s = Solver(w.shape, precision)
+    opts = Opts(tol=w.tol, max_iter=2000)
+    p = CurveProblem(s, Material(), quat, rho, Load(dt=w.dt), w.increments, opts, opts)
+    th = torch.tensor(Material().theta(), dtype=torch.float64, requires_grad=True)
+    tgt = torch.zeros(w.increments, dtype=torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = StressStrainCurve.apply(th, p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # target: the curve of parameters theta0 * (1.05, 0.95, 1.05, 0.95) would need a
+    # second forward; the timing does not depend on the target values
+    L = curve_loss(c, tgt + c.detach() * 1.01)
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    print(f"# adjoint {precision}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s", file=sys.stderr,
+          flush=True)
+    return {"workload": f"{w.shape[0]}^3, {w.n_grains} grains, {w.increments} increments",
+            "precision": precision, "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "adjoint_over_forward": (t2 - t1) / (t1 - t0),
+            "checkpoint_every": int(np.ceil(np.sqrt(w.increments))),
+            "grad": th.grad.numpy().tolist()}
+
+
+def source_hash():
+    """Prefix of the sha256 of the device sources (matches the profiles)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_math.h", "fft_lds.h"):
+        with open(os.path.join(ROOT, "paper_1509_04953_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "fftevp_128cube_hbm_traffic.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    src = source_hash()
+    for ln in lines:
+        f = ln.split()
+        if len(f) >= 3 and f[0] == "traffic" and f[1] == kernel and f[2] == precision:
+            kv = dict(x.split("=", 1) for x in f[3:])
+            if kv.get("sources") != src:
+                return None
+            return (float(kv["fetch_kib"]) * float(kv["fetch_factor"])
+                    + float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+    return None
+
+
 def roofline(w, res, word):
     by = kernel_bytes(w.shape, word)
     prof = res["prof"]
@@ -86,8 +150,10 @@ def roofline(w, res, word):
     per_kernel = {k: {"avg_ms": prof[k][0] / max(prof[k][1], 1), "launches": prof[k][1],
                       "GBps": by[k] / (prof[k][0] / max(prof[k][1], 1) * 1e-3) / 1e9}
                   for k in by}
+    prec = "fp64" if word == 8 else "mixed"
     return {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": stored_traffic("k_" + dom, prec),
             "bytes_per_launch": by[dom], "avg_ms": avg}, per_kernel
 
 
@@ -142,6 +208,9 @@ def main():
     ap.add_argument("--workload", default="cu128")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solve is built and measured for a single MI355X; "
@@ -150,6 +219,14 @@ def main():
     import torch
     import synth
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copies": 3}))
+        return
     w = synth.workload(args.workload)
     quat, rho, _ = synth.make_microstructure(w)
     quat = quat.reshape(4, -1)
@@ -163,7 +240,7 @@ def main():
     word = 8 if main_p == "fp64" else 4
     roof, per_kernel = roofline(w, r, word)
     line = {
-        "metric": "FFT-EVP voxel-iterations/s at 128^3",
+        "metric": "FFT-EVP voxel-iterations/s at 128\u00b3 (FP64 vs mixed), adjoint/forward time",
         "value": r["rate"],
         "unit": "voxel-iterations/s",
         "n_gpus": 1,
@@ -190,6 +267,10 @@ def main():
                          "iterations": sum(m["iters"]), "roofline": mroof, "kernels": mk,
                          "s33_rel_diff_vs_fp64": float(np.max(np.abs(np.array(m["s33"]) - np.array(r["s33"])))
                                                        / np.max(np.abs(r["s33"])))}
+    if not args.no_adjoint:
+        wa = synth.workload("cu128adj")
+        qa, ra, _ = synth.make_microstructure(wa)
+        line["adjoint"] = run_adjoint(wa, qa.reshape(4, -1), ra.reshape(-1), "fp64")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, quat, rho)
     print(json.dumps(line), flush=True)
