@@ -51,6 +51,7 @@ struct fftevp_ctx {
   int ec = 0;          // committed strain buffer
   int e_last = 0;      // strain buffer written by the latest iteration
   double* partial = nullptr;
+  double* stage1 = nullptr;  // [NPART][<= 64] first-stage sums of the y pass
   int local_nb = 0, red_nb = 0;
   Ctl* ctl = nullptr;
   Ctl* ctl_h = nullptr;  // pinned
@@ -119,14 +120,14 @@ hipError_t timed(fftevp_ctx* c, int cls, int iter, F&& f) {
 }
 
 // After a stream synchronisation: accumulate the launches that did work.
-// Iteration i ran its local solve and reduction if i < iters, and its
-// spectral passes if it did not stop (i < iters - 1, or i < iters when the
-// loop ended without converging).
+// Iteration i ran its local solve, forward y pass and z pass (which holds the
+// stop test) if i < iters, and its inverse y pass if it did not stop
+// (i < iters - 1, or i < iters when the loop ended without converging).
 hipError_t harvest(fftevp_ctx* c, int iters, bool stopped) {
   for (const auto& r : c->recs) {
     bool did = r.iter < 0;
     if (r.iter >= 0) {
-      if (r.cls <= 1) did = r.iter < iters;
+      if (r.cls <= 3) did = r.iter < iters;
       else did = r.iter < (stopped ? iters - 1 : iters);
     }
     if (!did) continue;
@@ -257,6 +258,7 @@ fftevp_status alloc_all(fftevp_ctx* ctx) {
   const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->partial, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->ctl, sizeof(Ctl));
+  if (e == hipSuccess) e = al((void**)&ctx->stage1, NPART * 64 * sizeof(double));
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->red2, 8 * sizeof(double));
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->red2_h, 8 * sizeof(double), hipHostMallocDefault);
@@ -282,6 +284,7 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.a_sigt);
   f(ctx->b.a_rho);
   f(ctx->partial);
+  f(ctx->stage1);
   f(ctx->ctl);
   for (auto e : ctx->evpool) (void)hipEventDestroy(e);
   f(ctx->red2);
@@ -318,15 +321,24 @@ hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, co
   la.m = m;
   hipError_t e = timed(ctx, 0, i, [&] { return launch_local<T, MODE>(ctx->n0, la, ctx->stream); });
   if (e != hipSuccess) return e;
-  e = timed(ctx, 1, i, [&] { return launch_finalize(fin, ctx->stream); });
-  if (e != hipSuccess) return e;
-  YArgs<T> ya{(const C*)ctx->b.tmain, (C*)ctx->b.tmain, (const C*)ctx->b.tw[1], ctx->ctl, ctx->n0 / 2};
+  YArgs<T> ya{};
+  ya.src = (const C*)ctx->b.tmain;
+  ya.dst = (C*)ctx->b.tmain;
+  ya.tw = (const C*)ctx->b.tw[1];
+  ya.ctl = ctx->ctl;
+  ya.h = ctx->n0 / 2;
+  ya.partial = ctx->partial;
+  ya.nb_local = ctx->local_nb;
+  ya.stage1 = ctx->stage1;
   e = timed(ctx, 2, i, [&] { return launch_ypass<T, false>(ctx->n1, ctx->n2, ya, ctx->stream); });
   if (e != hipSuccess) return e;
   ZArgs<T> za{};
   za.buf = (C*)ctx->b.tmain;
   za.tw = (const C*)ctx->b.tw[2];
   za.ctl = ctx->ctl;
+  za.stage1 = ctx->stage1;
+  za.n_stage1 = ypass_tiles<T>(ctx->n1, ctx->n0 / 2);
+  za.fin = fin;
   za.h = ctx->n0 / 2;
   za.n1 = ctx->n1;
   za.inv_n0 = 1.0 / ctx->n0;
@@ -340,8 +352,12 @@ hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, co
   za.ci_s = m.ci_s;
   e = timed(ctx, 3, i, [&] { return launch_zgamma<T>(ctx->n2, za, ctx->stream); });
   if (e != hipSuccess) return e;
-  YArgs<T> yi{(const C*)ctx->b.tmain, (C*)ctx->b.emain[out_buf], (const C*)ctx->b.tw[1], ctx->ctl,
-              ctx->n0 / 2};
+  YArgs<T> yi{};
+  yi.src = (const C*)ctx->b.tmain;
+  yi.dst = (C*)ctx->b.emain[out_buf];
+  yi.tw = (const C*)ctx->b.tw[1];
+  yi.ctl = ctx->ctl;
+  yi.h = ctx->n0 / 2;
   return timed(ctx, 4, i, [&] { return launch_ypass<T, true>(ctx->n1, ctx->n2, yi, ctx->stream); });
 }
 

@@ -151,8 +151,8 @@ __device__ __forceinline__ T resolved(const T (&s)[6]) {
 // binary-exponent loop with a uniform trip count. Otherwise
 // |x|^(n-1) = exp((n-1) log|x|). Systems are processed four at a time to
 // bound the number of live registers.
-template <bool INTN, int G, typename T>
-__device__ __forceinline__ void flow_group(const T (&s)[6], T itauc, T n, int n_int, T (&w)[12],
+template <bool INTN, int G, typename T, typename W>
+__device__ __forceinline__ void flow_group(const T (&s)[6], T itauc, T n, int n_int, W (&w)[12],
                                            T (&g)[6], T& visc, T& asum) {
   T x[4], wg[4];
   static_for<0, 4>([&](auto ac) {
@@ -186,7 +186,7 @@ __device__ __forceinline__ void flow_group(const T (&s)[6], T itauc, T n, int n_
     constexpr int A = decltype(ac)::value;
     const T ax = fabs(x[A]);
     const T p = wg[A] * ax;
-    w[4 * G + A] = wg[A];
+    w[4 * G + A] = W(wg[A]);
     visc += p * ax;
     asum += p;
     const T sp = x[A] < T(0) ? -p : p;
@@ -197,8 +197,8 @@ __device__ __forceinline__ void flow_group(const T (&s)[6], T itauc, T n, int n_
   });
 }
 
-template <bool INTN, typename T>
-__device__ __forceinline__ void flow_eval(const T (&s)[6], T itauc, T n, int n_int, T (&w)[12],
+template <bool INTN, typename T, typename W>
+__device__ __forceinline__ void flow_eval(const T (&s)[6], T itauc, T n, int n_int, W (&w)[12],
                                           T (&g)[6], T& visc, T& asum) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = T(0);
@@ -223,9 +223,12 @@ __device__ __forceinline__ void cubic_mul(T d, T o, T sh, const T (&v)[6], T (&o
 // residual and potential of the local problem in the crystal frame:
 //   r   = A s - b + c1 * m(g)
 //   phi = 1/2 s.A s - b.s + c1 tauc/(n+1) visc
+// The residual is formed in T (it cancels large terms); once formed it is
+// returned in FP32 with the Jacobian weights w: the Newton direction is an
+// FP32 solve, and rounding a small residual keeps its relative precision.
 template <bool INTN, typename T>
 __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], const T (&b)[6],
-                                               T tauc, T itauc, T (&w)[12], T (&r)[6], T& phi) {
+                                               T tauc, T itauc, float (&w)[12], float (&r)[6], T& phi) {
   T g[6], visc, asum;
   flow_eval<INTN>(s, itauc, T(M.n), M.n_int, w, g, visc, asum);
   T As[6];
@@ -235,7 +238,7 @@ __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], co
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const T u = k < 3 ? T(kUN) : T(kUS);
-    r[k] = As[k] - b[k] + c1 * u * g[k];
+    r[k] = float(As[k] - b[k] + c1 * u * g[k]);
     q += s[k] * (T(0.5) * As[k] - b[k]);
   }
   phi = q + c1 * tauc / (T(M.n) + T(1)) * visc;
@@ -245,6 +248,7 @@ __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], co
 // assembled entry by entry in precision JT.
 template <typename JT, typename T>
 __device__ __forceinline__ void local_jacobian(const Mat& M, const T (&w)[12], T cj, JT (&J)[21]) {
+  // T: type of the weights and of the assembly
   static_for<0, 6>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     static_for<0, I + 1>([&](auto jc) {

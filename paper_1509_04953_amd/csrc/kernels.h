@@ -65,13 +65,21 @@ struct YArgs {
   const cx<T>* tw;
   const Ctl* ctl;
   int h;  // n0 / 2
+  // forward pass only: first-stage reduction of the local kernel's partials
+  // by an extra row of blocks, [NPART][n_stage1] out
+  const double* partial;
+  int nb_local;
+  double* stage1;
 };
 
 template <typename T>
 struct ZArgs {
   cx<T>* buf;
   const cx<T>* tw;
-  const Ctl* ctl;
+  Ctl* ctl;
+  const double* stage1;  // [NPART][n_stage1] partial sums from the y pass
+  int n_stage1;
+  FinArgs fin;           // stop test and mixed-BC update, done by the block holding xi = 0
   int h, n1;
   double inv_n0, inv_n1, inv_n2, inv_ntot;
   double c0l, c0m, ci_d, ci_o, ci_s;
@@ -117,11 +125,12 @@ template <typename T, int MODE>
 hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s);
 template <typename T>
 int local_blocks(int n0, int n1, int n2);
+template <typename T>
+int ypass_tiles(int n1, int h);
 template <typename T, bool INV>
 hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s);
-hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
 template <typename T>

@@ -6,12 +6,14 @@
 //              (LDS), local Newton solve per voxel (registers), polarisation
 //              tau = sigma - C0:eps, forward real FFT along x (LDS); FP64
 //              partial sums of the residual and the mean stress.
-//   k_finalize one block: reduction of the partial sums in a fixed order,
-//              stop test, update of the macroscopic strain of the
-//              stress-controlled components (mixed boundary conditions).
-//   k_ypass    forward FFT along y (tiles of x-frequencies, LDS).
+//   k_ypass    forward FFT along y (tiles of x-frequencies, LDS); an extra
+//              row of blocks reduces the partial sums (first stage, fixed
+//              order) at the same time.
 //   k_zgamma   forward FFT along z, Green operator per frequency, inverse
-//              FFT along z, for all six components at once (LDS).
+//              FFT along z, for all six components at once (LDS). The block
+//              holding xi = 0 first finishes the reduction, tests for
+//              convergence and updates the macroscopic strain of the
+//              stress-controlled components (mixed boundary conditions).
 //   k_ypass    inverse FFT along y into the next strain buffer.
 // The x-Nyquist plane never needs y/z transforms: there the Green operator
 // is the constant C0^-1, so k_local writes the next strain's Nyquist plane
@@ -102,14 +104,19 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
   }
 }
 
+// minimum waves per SIMD requested from the register allocator
 #ifndef FFTEVP_LOCAL_WAVES
 #define FFTEVP_LOCAL_WAVES 1
+#endif
+#ifndef FFTEVP_LOCAL_WAVES_F32
+#define FFTEVP_LOCAL_WAVES_F32 4
 #endif
 
 // INTN: the rate exponent is a positive integer (compile-time choice of the
 // power evaluation; the host picks the instance).
 template <typename T, int N0, int MODE, bool INTN>
-__global__ __launch_bounds__(256, FFTEVP_LOCAL_WAVES) void k_local(LocalArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32) void k_local(
+    LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
   if (a.ctl && a.ctl->done) return;
   __shared__ cx<T> sh[3 * S::LPB * S::LS];
@@ -190,24 +197,26 @@ __global__ __launch_bounds__(256, FFTEVP_LOCAL_WAVES) void k_local(LocalArgs<T> 
       // of the residual: each pass evaluates the candidate, then either
       // halves the step (line search) or accepts it and computes the next
       // Newton direction from the accepted point's tangent.
-      T w[12], r[6], d[6];
-      T phi = T(0), slope = T(0), rn2 = T(0), step = T(0);
-      const T cj = T(M.c1) * T(M.n) * itauc;
+      float w[12], r[6], d[6];
+      T phi = T(0);
+      float slope = 0.f, rn2 = 0.f;
+      T step = T(0);
+      const float cj = float(T(M.c1) * T(M.n) * itauc);
       const T ntol2 = T(M.ntol) * T(M.ntol), qtol2 = T(M.qtol) * T(M.qtol);
       bool conv = false, first = true;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) d[k] = T(0);
+      for (int k = 0; k < 6; ++k) d[k] = 0.f;
 #pragma unroll 1
       for (int pass = 0; pass < 64 * M.newton_max; ++pass) {
         T phi1, cand[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * d[k];
+        for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * T(d[k]);
         local_residual<INTN>(M, cand, b, tauc, itauc, w, r, phi1);
-        T rn1 = T(0);
+        float rn1 = 0.f;
 #pragma unroll
         for (int k = 0; k < 6; ++k) rn1 += r[k] * r[k];
         if (!first) {
-          const bool ok = isfinite(phi1) && (phi1 <= phi + T(1e-4) * step * slope || rn1 <= T(0.25) * rn2);
+          const bool ok = isfinite(phi1) && (phi1 <= phi + T(1e-4) * step * T(slope) || rn1 <= 0.25f * rn2);
           if (!ok && step > T(1e-12)) {
             step *= T(0.5);
             ++nls;
@@ -216,15 +225,14 @@ __global__ __launch_bounds__(256, FFTEVP_LOCAL_WAVES) void k_local(LocalArgs<T> 
           T dn2 = T(0), sn2 = T(0);
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
-            const T dk = step * d[k];
+            const T dk = step * T(d[k]);
             dn2 += dk * dk;
             sc[k] = cand[k];
             sn2 += cand[k] * cand[k];
           }
           ++nit;
-          // a full Newton step this small leaves an error of its square
           const T sc2 = fmax(sn2, T(1));
-          if (dn2 <= ntol2 * sc2 || (step == T(1) && dn2 <= qtol2 * sc2)) {
+          if (dn2 <= ntol2 * sc2) {
             conv = true;
             break;
           }
@@ -236,22 +244,37 @@ __global__ __launch_bounds__(256, FFTEVP_LOCAL_WAVES) void k_local(LocalArgs<T> 
         {
           // Newton direction in FP32: the residual, line search and stop
           // test stay in T, so the converged stress is the T-precision root
-          float J[21], mr[6], df[6];
+          float J[21], mr[6];
           local_jacobian<float>(M, w, cj, J);
 #pragma unroll
-          for (int k = 0; k < 6; ++k) mr[k] = -float(r[k]);
-          ldl_solve(J, mr, df);
-#pragma unroll
-          for (int k = 0; k < 6; ++k) d[k] = T(df[k]);
+          for (int k = 0; k < 6; ++k) mr[k] = -r[k];
+          ldl_solve(J, mr, d);
         }
-        slope = T(0);
+        // a full step this small is in the quadratic regime: take it without
+        // evaluating the candidate (its error is of the step's square)
+        {
+          T dn2 = T(0), sn2 = T(0);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            dn2 += T(d[k]) * T(d[k]);
+            sn2 += sc[k] * sc[k];
+          }
+          if (dn2 <= qtol2 * fmax(sn2, T(1))) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sc[k] += T(d[k]);
+            ++nit;
+            conv = true;
+            break;
+          }
+        }
+        slope = 0.f;
 #pragma unroll
         for (int k = 0; k < 6; ++k) slope += r[k] * d[k];
         step = T(1);
       }
       fail = conv ? 0 : 1;
     } else {  // MODE_TANGENT: linear solve with the tangent at the given stress
-      T R[9], st[6], stc[6], w[12], g6[6], visc, asum, J[21];
+      T R[9], st[6], stc[6], w[12], g6[6], visc, asum, J[21];  // full precision tangent
       rot(R);
 #pragma unroll
       for (int k = 0; k < 6; ++k) st[k] = a.sig_t[(size_t)k * vox + g];
@@ -337,13 +360,34 @@ __global__ __launch_bounds__(256, FFTEVP_LOCAL_WAVES) void k_local(LocalArgs<T> 
 // ---------------------------------------------------------------------------
 // y pass: FFT along y of tiles of TX consecutive x-frequencies
 // ---------------------------------------------------------------------------
+// The forward pass has one extra row of blocks (blockIdx.y == 0): block b of
+// that row reduces a contiguous share of the local kernel's per-block partial
+// sums, in a fixed order, while the other rows transform.
 template <typename T, int N1, int TX, bool INV>
 __global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
   if (a.ctl && a.ctl->done) return;
+  if constexpr (!INV) {
+    if (blockIdx.y == 0) {
+      const int ns = gridDim.x, nb = a.nb_local;
+      const int chunk = (nb + ns - 1) / ns;
+      const int b0 = blockIdx.x * chunk, b1 = min(nb, b0 + chunk);
+      double v[NPART];
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) v[k] = 0.0;
+      for (int b = b0 + threadIdx.x; b < b1; b += 256) {
+#pragma unroll
+        for (int k = 0; k < NPART - 1; ++k) v[k] += a.partial[(size_t)k * nb + b];
+        v[NPART - 1] = fmax(v[NPART - 1], a.partial[(size_t)(NPART - 1) * nb + b]);
+      }
+      block_reduce<NPART, 1>(v, a.stage1 + blockIdx.x, ns);
+      return;
+    }
+  }
   constexpr int LS = N1 + 1;
   __shared__ cx<T> sh[TX * LS];
   const int H = a.h;
-  const size_t base = (size_t)blockIdx.y * N1 * H + (size_t)blockIdx.x * TX;
+  const size_t cz = INV ? blockIdx.y : blockIdx.y - 1;
+  const size_t base = cz * N1 * H + (size_t)blockIdx.x * TX;
   const cx<T>* __restrict__ src = a.src + base;
   cx<T>* __restrict__ dst = a.dst + base;
   for (int idx = threadIdx.x; idx < N1 * TX; idx += 256) {
@@ -387,9 +431,30 @@ __device__ __forceinline__ void apply_gamma(cx<T> (&t)[6], T nx, T ny, T nz, T c
 
 template <typename T, int N2, int TX>
 __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
-  if (a.ctl && a.ctl->done) return;
+  if (a.ctl->done) return;
   constexpr int LS = N2 + 1;
   __shared__ cx<T> sh[6 * TX * LS];
+  __shared__ double E_sh[6];
+  // the block holding xi = 0 finishes the reduction, tests for convergence
+  // and updates the macroscopic strain before using it
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    __shared__ double tot[NPART];
+    if (threadIdx.x < NPART) {
+      const int k = threadIdx.x;
+      double r = a.stage1[(size_t)k * a.n_stage1];
+      for (int b = 1; b < a.n_stage1; ++b) {
+        const double x = a.stage1[(size_t)k * a.n_stage1 + b];
+        r = (k == NPART - 1) ? fmax(r, x) : r + x;
+      }
+      tot[k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      finalize_sums(a.fin, a.ctl, tot);
+      for (int k = 0; k < 6; ++k) E_sh[k] = a.ctl->E[k];
+    }
+    __syncthreads();
+  }
   const int H = a.h, n1 = a.n1;
   const size_t cs = (size_t)N2 * n1 * H;  // component stride (complex)
   const int ky = blockIdx.y, kx0 = blockIdx.x * TX;
@@ -418,7 +483,7 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
     const int kxg = kx0 + kx;
     if (kxg == 0 && ky == 0 && z == 0) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) t[c] = {T(a.ctl->E[c]), T(0)};
+      for (int c = 0; c < 6; ++c) t[c] = {T(E_sh[c]), T(0)};
     } else if (nyq_y || 2 * z == N2) {
       cx<T> o[6];
       T re[6], im[6], ro[6], io[6];
@@ -454,35 +519,9 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// reduction, stop test and mixed-BC update: one block of 1024 threads
+// stop test and mixed-BC update from the reduced sums (one thread)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finalize(FinArgs a) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
-  double v[NPART];
-#pragma unroll
-  for (int k = 0; k < NPART; ++k) v[k] = 0.0;
-  const int nb = a.nblocks;
-  for (int b = threadIdx.x; b < nb; b += 1024) {
-#pragma unroll
-    for (int k = 0; k < NPART - 1; ++k) v[k] += a.partial[(size_t)k * nb + b];
-    v[NPART - 1] = fmax(v[NPART - 1], a.partial[(size_t)(NPART - 1) * nb + b]);
-  }
-  __shared__ double red[16][NPART];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NPART; ++k) {
-    const double r = (k == NPART - 1) ? wave_max(v[k]) : wave_sum(v[k]);
-    if (lane == 0) red[wv][k] = r;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double tot[NPART];
-  for (int k = 0; k < NPART; ++k) {
-    double r = red[0][k];
-    for (int w = 1; w < 16; ++w) r = (k == NPART - 1) ? fmax(r, red[w][k]) : r + red[w][k];
-    tot[k] = r;
-  }
+__device__ void finalize_sums(const FinArgs& a, Ctl* ctl, const double (&tot)[NPART]) {
   const double iv = 1.0 / a.nvox;
   double Sig[6], nE = 0.0, nS = 0.0, nbc = 0.0, dS[6];
   for (int k = 0; k < 6; ++k) {
@@ -515,11 +554,6 @@ __global__ __launch_bounds__(1024) void k_finalize(FinArgs a) {
       ctl->E[i] += s;
     }
   }
-}
-
-hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, a);
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -801,8 +835,15 @@ hipError_t ypass_tx(int n2, const YArgs<T>& a, hipStream_t s) {
   if constexpr (TX > 1) {
     if (a.h < TX) return ypass_tx<T, N, TX / 2, INV>(n2, a, s);
   }
-  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, 6 * n2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, 6 * n2 + (INV ? 0 : 1)), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// number of x-frequency tiles of a y pass (= blocks in its reduction row)
+template <typename T>
+int ypass_tiles(int n1, int h) {
+  const int txm = (sizeof(T) == 8 ? 16 : 32) / (n1 >= 512 ? 2 : 1);
+  return h / (h < txm ? h : txm);
 }
 
 template <typename T, bool INV>
@@ -821,11 +862,15 @@ hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s) {
   }
 }
 
+#ifndef FFTEVP_ZLDS_KB
+#define FFTEVP_ZLDS_KB 50
+#endif
+
 template <typename T>
 constexpr int z_tile(int n2) {
-  // six components of TX z-lines in LDS: 6 * TX * (n2 + 1) complex <= ~100 KB
+  // six components of TX z-lines in LDS: 6 * TX * (n2 + 1) complex within the budget
   int tx = 16;
-  while (tx > 1 && 6 * tx * (n2 + 1) * 2 * (int)sizeof(T) > 100 * 1024) tx /= 2;
+  while (tx > 1 && 6 * tx * (n2 + 1) * 2 * (int)sizeof(T) > FFTEVP_ZLDS_KB * 1024) tx /= 2;
   return tx;
 }
 
@@ -892,6 +937,7 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_local<T, MODE_TANGENT>(int, const LocalArgs<T>&, hipStream_t);    \
   template hipError_t launch_local<T, MODE_EXPORT>(int, const LocalArgs<T>&, hipStream_t);     \
   template int local_blocks<T>(int, int, int);                                                  \
+  template int ypass_tiles<T>(int, int);                                                        \
   template hipError_t launch_ypass<T, false>(int, int, const YArgs<T>&, hipStream_t);          \
   template hipError_t launch_ypass<T, true>(int, int, const YArgs<T>&, hipStream_t);           \
   template hipError_t launch_zgamma<T>(int, const ZArgs<T>&, hipStream_t);                     \
