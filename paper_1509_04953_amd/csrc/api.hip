@@ -64,7 +64,7 @@ struct fftevp_ctx {
   int adj_iters = 0;
   std::string err;
   // kernel timing
-  bool prof = false;
+  unsigned prof = 0;  // bit k: time kernel class k
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   struct Rec {
@@ -108,7 +108,7 @@ hipError_t ev_pair(fftevp_ctx* c, hipEvent_t* a, hipEvent_t* b) {
 // launch that always does work.
 template <typename F>
 hipError_t timed(fftevp_ctx* c, int cls, int iter, F&& f) {
-  if (!c->prof) return f();
+  if (!((c->prof >> cls) & 1u)) return f();
   hipEvent_t a, b;
   hipError_t e = ev_pair(c, &a, &b);
   if (e != hipSuccess) return e;
@@ -863,9 +863,9 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   return FFTEVP_OK;
 }
 
-fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int enable) {
+fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int class_mask) {
   if (!ctx) return FFTEVP_EINVAL;
-  ctx->prof = enable != 0;
+  ctx->prof = (unsigned)class_mask & ((1u << FFTEVP_NPROF) - 1u);
   return FFTEVP_OK;
 }
 

@@ -75,28 +75,31 @@ struct LocalShape {
 
 // Load the x-half-spectra of the six strain components of this block's lines
 // and pack them pairwise as Z = Xa + i Xb over the full length N0 (Hermitian
-// extension), ready for one inverse complex FFT per pair.
+// extension), ready for one inverse complex FFT per pair. Spectra are stored
+// with the six components innermost, so a line is one contiguous block.
 template <typename T, int N0>
 __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, const T* __restrict__ nyq,
-                                            size_t line0, size_t vox, size_t planes, cx<T>* sh) {
+                                            size_t line0, cx<T>* sh) {
   using S = LocalShape<T, N0>;
   constexpr int PER_LINE = S::H + 1;
+  // spectra are [line][k][component]: thread idx takes pair p of (l, k)
   for (int idx = threadIdx.x; idx < 3 * S::LPB * PER_LINE; idx += S::NT) {
-    const int p = idx / (S::LPB * PER_LINE);
-    const int rem = idx - p * (S::LPB * PER_LINE);
-    const int l = rem / PER_LINE, k = rem - l * PER_LINE;
+    const int l = idx / (3 * PER_LINE);
+    const int rem = idx - l * (3 * PER_LINE);
+    const int k = rem / 3, p = rem - (rem / 3) * 3;
     const size_t line = line0 + l;
     cx<T> xa, xb;
     if (k < S::H) {
-      xa = main[(size_t)(2 * p) * (vox / 2) + line * S::H + k];
-      xb = main[(size_t)(2 * p + 1) * (vox / 2) + line * S::H + k];
+      const cx<T>* src = main + (line * S::H + k) * 6 + 2 * p;
+      xa = src[0];
+      xb = src[1];
       if (k == 0) {
         xa.y = T(0);
         xb.y = T(0);
       }
     } else {
-      xa = {nyq[(size_t)(2 * p) * planes + line], T(0)};
-      xb = {nyq[(size_t)(2 * p + 1) * planes + line], T(0)};
+      xa = {nyq[line * 6 + 2 * p], T(0)};
+      xb = {nyq[line * 6 + 2 * p + 1], T(0)};
     }
     cx<T>* Z = sh + (p * S::LPB + l) * S::LS;
     Z[k] = {xa.x - xb.y, xa.y + xb.x};
@@ -104,7 +107,6 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
   }
 }
 
-// minimum waves per SIMD requested from the register allocator
 #ifndef FFTEVP_LOCAL_WAVES
 #define FFTEVP_LOCAL_WAVES 1
 #endif
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
   const size_t line0 = (size_t)blockIdx.x * S::LPB;
   const Mat& M = a.m;
 
-  load_packed<T, N0>(a.e_main, a.e_nyq, line0, vox, planes, sh);
+  load_packed<T, N0>(a.e_main, a.e_nyq, line0, sh);
   __syncthreads();
   fft_lines<T, N0, true, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
 
@@ -328,16 +330,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
 
   // unpack: Xa[k] = (Z[k] + conj Z[N-k]) / 2, Xb[k] = (Z[k] - conj Z[N-k]) / 2i
   for (int idx = threadIdx.x; idx < 3 * S::LPB * S::H; idx += S::NT) {
-    const int p = idx / (S::LPB * S::H);
-    const int rem = idx - p * (S::LPB * S::H);
-    const int l = rem / S::H, k = rem - l * S::H;
+    const int l = idx / (3 * S::H);
+    const int rem = idx - l * (3 * S::H);
+    const int k = rem / 3, p = rem - (rem / 3) * 3;
     const cx<T>* Z = sh + (p * S::LPB + l) * S::LS;
     const cx<T> zk = Z[k], zm = Z[(N0 - k) & (N0 - 1)];
     const cx<T> xa = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     const cx<T> xb = {T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
-    const size_t line = line0 + l;
-    a.t_main[(size_t)(2 * p) * (vox / 2) + line * S::H + k] = xa;
-    a.t_main[(size_t)(2 * p + 1) * (vox / 2) + line * S::H + k] = xb;
+    cx<T>* dst = a.t_main + ((line0 + l) * S::H + k) * 6 + 2 * p;
+    dst[0] = xa;
+    dst[1] = xb;
   }
   // x-Nyquist plane of the next strain: e = -C0^-1 tau_hat / n0 (real)
   if (threadIdx.x < S::LPB) {
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
     cubic_mul(ci_d, ci_o, ci_s, tn, en);
     const T s = -T(M.inv_n0);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a.e_nyq_next[(size_t)k * planes + line0 + l] = s * en[k];
+    for (int k = 0; k < 6; ++k) a.e_nyq_next[(line0 + l) * 6 + k] = s * en[k];
   }
   block_reduce<NPART, 1>(part, a.partial + blockIdx.x, gridDim.x);
 }
@@ -360,9 +362,47 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
 // ---------------------------------------------------------------------------
 // y pass: FFT along y of tiles of TX consecutive x-frequencies
 // ---------------------------------------------------------------------------
-// The forward pass has one extra row of blocks (blockIdx.y == 0): block b of
-// that row reduces a contiguous share of the local kernel's per-block partial
-// sums, in a fixed order, while the other rows transform.
+// LDS budget of the y and z passes; the tile width TX (x-frequencies per
+// block, six components each) is the largest power of two that fits.
+#ifndef FFTEVP_SPEC_LDS_KB
+#define FFTEVP_SPEC_LDS_KB 50
+#endif
+#ifndef FFTEVP_Y_LDS_KB
+#define FFTEVP_Y_LDS_KB 25
+#endif
+
+template <typename T>
+__host__ __device__ constexpr int spec_tile(int n, int kb = FFTEVP_SPEC_LDS_KB) {
+  int tx = 16;
+  while (tx > 1 && 6 * tx * (n + 1) * 2 * (int)sizeof(T) > kb * 1024) tx /= 2;
+  return tx;
+}
+template <typename T>
+__host__ __device__ constexpr int y_tile(int n) {
+  return spec_tile<T>(n, FFTEVP_Y_LDS_KB);
+}
+
+// Rows of W = 6 TX contiguous complex values (row stride rs) <-> W lines of
+// length N in LDS (line stride N + 1).
+template <typename T, int N, int W>
+__device__ __forceinline__ void rows_to_lines(const cx<T>* __restrict__ src, size_t rs, cx<T>* sh) {
+  for (int idx = threadIdx.x; idx < N * W; idx += 256) {
+    const int r = idx / W, w = idx - (idx / W) * W;
+    sh[w * (N + 1) + r] = src[(size_t)r * rs + w];
+  }
+}
+template <typename T, int N, int W>
+__device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict__ dst, size_t rs) {
+  for (int idx = threadIdx.x; idx < N * W; idx += 256) {
+    const int r = idx / W, w = idx - (idx / W) * W;
+    dst[(size_t)r * rs + w] = sh[w * (N + 1) + r];
+  }
+}
+
+// FFT along y of TX x-frequencies x 6 components. The forward pass has one
+// extra row of blocks (blockIdx.y == 0): block b of that row reduces a
+// contiguous share of the local kernel's per-block partial sums, in a fixed
+// order, while the other rows transform.
 template <typename T, int N1, int TX, bool INV>
 __global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
   if (a.ctl && a.ctl->done) return;
@@ -383,23 +423,15 @@ __global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
       return;
     }
   }
-  constexpr int LS = N1 + 1;
-  __shared__ cx<T> sh[TX * LS];
-  const int H = a.h;
-  const size_t cz = INV ? blockIdx.y : blockIdx.y - 1;
-  const size_t base = cz * N1 * H + (size_t)blockIdx.x * TX;
-  const cx<T>* __restrict__ src = a.src + base;
-  cx<T>* __restrict__ dst = a.dst + base;
-  for (int idx = threadIdx.x; idx < N1 * TX; idx += 256) {
-    const int y = idx / TX, kx = idx - (idx / TX) * TX;
-    sh[kx * LS + y] = src[(size_t)y * H + kx];
-  }
+  constexpr int W = 6 * TX;
+  __shared__ cx<T> sh[W * (N1 + 1)];
+  const size_t rs = (size_t)a.h * 6;  // y stride
+  const size_t z = INV ? blockIdx.y : blockIdx.y - 1;
+  const size_t base = z * N1 * rs + (size_t)blockIdx.x * W;
+  rows_to_lines<T, N1, W>(a.src + base, rs, sh);
   __syncthreads();
-  fft_lines<T, N1, INV, TX, LS, 256>(sh, a.tw);
-  for (int idx = threadIdx.x; idx < N1 * TX; idx += 256) {
-    const int y = idx / TX, kx = idx - (idx / TX) * TX;
-    dst[(size_t)y * H + kx] = sh[kx * LS + y];
-  }
+  fft_lines<T, N1, INV, W, N1 + 1, 256>(sh, a.tw);
+  lines_to_rows<T, N1, W>(sh, a.dst + base, rs);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,7 +465,8 @@ template <typename T, int N2, int TX>
 __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
   if (a.ctl->done) return;
   constexpr int LS = N2 + 1;
-  __shared__ cx<T> sh[6 * TX * LS];
+  constexpr int W = 6 * TX;
+  __shared__ cx<T> sh[W * LS];
   __shared__ double E_sh[6];
   // the block holding xi = 0 finishes the reduction, tests for convergence
   // and updates the macroscopic strain before using it
@@ -456,18 +489,12 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
     __syncthreads();
   }
   const int H = a.h, n1 = a.n1;
-  const size_t cs = (size_t)N2 * n1 * H;  // component stride (complex)
   const int ky = blockIdx.y, kx0 = blockIdx.x * TX;
-  cx<T>* __restrict__ buf = a.buf + (size_t)ky * H + kx0;
-  const size_t zs = (size_t)n1 * H;
-  for (int idx = threadIdx.x; idx < 6 * N2 * TX; idx += 256) {
-    const int c = idx / (N2 * TX);
-    const int rem = idx - c * (N2 * TX);
-    const int z = rem / TX, kx = rem - (rem / TX) * TX;
-    sh[(c * TX + kx) * LS + z] = buf[c * cs + z * zs + kx];
-  }
+  const size_t zs = (size_t)n1 * H * 6;  // z stride
+  cx<T>* __restrict__ buf = a.buf + ((size_t)ky * H + kx0) * 6;
+  rows_to_lines<T, N2, W>(buf, zs, sh);
   __syncthreads();
-  fft_lines<T, N2, false, 6 * TX, LS, 256>(sh, a.tw);
+  fft_lines<T, N2, false, W, LS, 256>(sh, a.tw);
 
   const T inv_n = T(a.inv_ntot);
   const T c_mu = T(1.0 / a.c0m), c_ratio = T((a.c0l + a.c0m) / (a.c0l + 2.0 * a.c0m));
@@ -479,7 +506,7 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
     const int kz_s = z < N2 / 2 ? z : z - N2;
     cx<T> t[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) t[c] = sh[(c * TX + kx) * LS + z];
+    for (int c = 0; c < 6; ++c) t[c] = sh[(kx * 6 + c) * LS + z];
     const int kxg = kx0 + kx;
     if (kxg == 0 && ky == 0 && z == 0) {
 #pragma unroll
@@ -506,16 +533,11 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
       for (int c = 0; c < 6; ++c) t[c] = {inv_n * t[c].x, inv_n * t[c].y};
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sh[(c * TX + kx) * LS + z] = t[c];
+    for (int c = 0; c < 6; ++c) sh[(kx * 6 + c) * LS + z] = t[c];
   }
   __syncthreads();
-  fft_lines<T, N2, true, 6 * TX, LS, 256>(sh, a.tw);
-  for (int idx = threadIdx.x; idx < 6 * N2 * TX; idx += 256) {
-    const int c = idx / (N2 * TX);
-    const int rem = idx - c * (N2 * TX);
-    const int z = rem / TX, kx = rem - (rem / TX) * TX;
-    buf[c * cs + z * zs + kx] = sh[(c * TX + kx) * LS + z];
-  }
+  fft_lines<T, N2, true, W, LS, 256>(sh, a.tw);
+  lines_to_rows<T, N2, W>(sh, buf, zs);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,9 +799,9 @@ __global__ __launch_bounds__(256) void k_export(const T* __restrict__ src, doubl
 template <typename T>
 __global__ __launch_bounds__(256) void k_shift_dc(cx<T>* main, size_t planes, int h, Shift6 d) {
   for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < 6 * planes; g += (size_t)gridDim.x * 256) {
-    const int c = (int)(g / planes);
-    const size_t line = g - c * planes;
-    main[(size_t)c * planes * h + line * h].x += (T)d.v[c];
+    const size_t line = g / 6;
+    const int c = (int)(g - line * 6);
+    main[line * h * 6 + c].x += (T)d.v[c];
   }
 }
 
@@ -829,49 +851,35 @@ int local_blocks(int n0, int n1, int n2) {
   return n1 * n2 / lpb;
 }
 
+// number of x-frequency tiles of a y pass (= blocks in its reduction row)
+template <typename T>
+int ypass_tiles(int n1, int h) {
+  const int tx = y_tile<T>(n1);
+  return h / (h < tx ? h : tx);
+}
+
 // Launch with the largest tile TX <= TXM that divides the h x-frequencies.
 template <typename T, int N, int TX, bool INV>
 hipError_t ypass_tx(int n2, const YArgs<T>& a, hipStream_t s) {
   if constexpr (TX > 1) {
     if (a.h < TX) return ypass_tx<T, N, TX / 2, INV>(n2, a, s);
   }
-  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, 6 * n2 + (INV ? 0 : 1)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, n2 + (INV ? 0 : 1)), dim3(256), 0, s, a);
   return hipGetLastError();
-}
-
-// number of x-frequency tiles of a y pass (= blocks in its reduction row)
-template <typename T>
-int ypass_tiles(int n1, int h) {
-  const int txm = (sizeof(T) == 8 ? 16 : 32) / (n1 >= 512 ? 2 : 1);
-  return h / (h < txm ? h : txm);
 }
 
 template <typename T, bool INV>
 hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s) {
-  // 16 B (FP64) or 8 B (FP32) complex: 256 B rows, LDS <= 64 KB
-  constexpr int B = sizeof(T) == 8 ? 16 : 32;
   switch (n1) {
-    case 8: return ypass_tx<T, 8, B, INV>(n2, a, s);
-    case 16: return ypass_tx<T, 16, B, INV>(n2, a, s);
-    case 32: return ypass_tx<T, 32, B, INV>(n2, a, s);
-    case 64: return ypass_tx<T, 64, B, INV>(n2, a, s);
-    case 128: return ypass_tx<T, 128, B, INV>(n2, a, s);
-    case 256: return ypass_tx<T, 256, B, INV>(n2, a, s);
-    case 512: return ypass_tx<T, 512, B / 2, INV>(n2, a, s);
+    case 8: return ypass_tx<T, 8, y_tile<T>(8), INV>(n2, a, s);
+    case 16: return ypass_tx<T, 16, y_tile<T>(16), INV>(n2, a, s);
+    case 32: return ypass_tx<T, 32, y_tile<T>(32), INV>(n2, a, s);
+    case 64: return ypass_tx<T, 64, y_tile<T>(64), INV>(n2, a, s);
+    case 128: return ypass_tx<T, 128, y_tile<T>(128), INV>(n2, a, s);
+    case 256: return ypass_tx<T, 256, y_tile<T>(256), INV>(n2, a, s);
+    case 512: return ypass_tx<T, 512, y_tile<T>(512), INV>(n2, a, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-#ifndef FFTEVP_ZLDS_KB
-#define FFTEVP_ZLDS_KB 50
-#endif
-
-template <typename T>
-constexpr int z_tile(int n2) {
-  // six components of TX z-lines in LDS: 6 * TX * (n2 + 1) complex within the budget
-  int tx = 16;
-  while (tx > 1 && 6 * tx * (n2 + 1) * 2 * (int)sizeof(T) > FFTEVP_ZLDS_KB * 1024) tx /= 2;
-  return tx;
 }
 
 template <typename T, int N, int TX>
@@ -886,13 +894,13 @@ hipError_t zgamma_tx(const ZArgs<T>& a, hipStream_t s) {
 template <typename T>
 hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s) {
   switch (n2) {
-    case 8: return zgamma_tx<T, 8, z_tile<T>(8)>(a, s);
-    case 16: return zgamma_tx<T, 16, z_tile<T>(16)>(a, s);
-    case 32: return zgamma_tx<T, 32, z_tile<T>(32)>(a, s);
-    case 64: return zgamma_tx<T, 64, z_tile<T>(64)>(a, s);
-    case 128: return zgamma_tx<T, 128, z_tile<T>(128)>(a, s);
-    case 256: return zgamma_tx<T, 256, z_tile<T>(256)>(a, s);
-    case 512: return zgamma_tx<T, 512, z_tile<T>(512)>(a, s);
+    case 8: return zgamma_tx<T, 8, spec_tile<T>(8)>(a, s);
+    case 16: return zgamma_tx<T, 16, spec_tile<T>(16)>(a, s);
+    case 32: return zgamma_tx<T, 32, spec_tile<T>(32)>(a, s);
+    case 64: return zgamma_tx<T, 64, spec_tile<T>(64)>(a, s);
+    case 128: return zgamma_tx<T, 128, spec_tile<T>(128)>(a, s);
+    case 256: return zgamma_tx<T, 256, spec_tile<T>(256)>(a, s);
+    case 512: return zgamma_tx<T, 512, spec_tile<T>(512)>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

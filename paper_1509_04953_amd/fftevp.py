@@ -20,7 +20,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENONFINITE, ELOCAL, ESTATE = 0, 1, -1, 
 FP64, MIXED = 0, 1
 FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5}
 NPROF = 7
-PROF_NAMES = ("local", "finalize", "yfwd", "zgamma", "yinv", "state", "adjoint_setup")
+PROF_NAMES = ("local", "unused", "yfwd", "zgamma", "yinv", "state", "adjoint")
 NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6}
 
 
@@ -228,8 +228,15 @@ class Solver:
     def load_state(self, buf):
         self._check(self.lib.fftevp_load_state(self.h, C.c_void_p(buf.data_ptr())))
 
-    def set_profiling(self, on: bool):
-        self._check(self.lib.fftevp_set_profiling(self.h, int(bool(on))))
+    def set_profiling(self, on, classes=None):
+        """Time kernel classes with HIP events: all when ``classes`` is None,
+        else the given names from PROF_NAMES."""
+        mask = 0
+        if on:
+            names = PROF_NAMES if classes is None else classes
+            for n in names:
+                mask |= 1 << PROF_NAMES.index(n)
+        self._check(self.lib.fftevp_set_profiling(self.h, mask))
 
     def profile(self, reset=True):
         """Per kernel class: (summed ms, launches) from HIP events."""

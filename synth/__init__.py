@@ -142,15 +142,23 @@ def grain_boundary_nuclei(grains: np.ndarray, rho: np.ndarray, fraction: float,
     out = rho.copy()
     covered = np.zeros(grains.shape, dtype=bool)
     target = fraction * grains.size
-    zz, yy, xx = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
-    while covered.sum() < target and gb_idx.size:
+    count = 0
+    while count < target and gb_idx.size:
         c = gb_idx[rng.integers(gb_idx.size)]
         cz, cy, cx = np.unravel_index(c, grains.shape)
         r = rng.uniform(*radius)
-        dz = (zz - cz + n2 // 2) % n2 - n2 // 2
-        dy = (yy - cy + n1 // 2) % n1 - n1 // 2
-        dx = (xx - cx + n0 // 2) % n0 - n0 // 2
-        covered |= dx * dx + dy * dy + dz * dz <= r * r
+        # voxels within periodic distance r of the centre, found in the
+        # centre's bounding box (wrapped indices)
+        k = int(np.ceil(r))
+        off = np.arange(-k, k + 1)
+        dz, dy, dx = np.meshgrid(off, off, off, indexing="ij")
+        inside = dx * dx + dy * dy + dz * dz <= r * r
+        zi = (cz + dz[inside]) % n2
+        yi = (cy + dy[inside]) % n1
+        xi = (cx + dx[inside]) % n0
+        new = ~covered[zi, yi, xi]
+        covered[zi, yi, xi] = True
+        count += int(new.sum())
     out[covered] = rho_nuc
     return out
 

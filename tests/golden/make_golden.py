@@ -10,6 +10,9 @@
 * curve_16cube.json: the mean-stress curve of the 16^3 eight-grain
   polycrystal (uniform density) over 5 increments.
 Both solve each increment to a stop tolerance of 1e-13.
+* curve_64cube.json: the 64^3, 100-grain, log-normal-density polycrystal
+  over its first 3 increments at the workload's stop tolerance 1e-6, with
+  the iteration counts and sampled fields (slow: about 10 minutes).
 """
 import json
 import os
@@ -49,8 +52,29 @@ def curve16():
             "E33": [r["E"][2] for r in reps], "tol": 1e-13}
 
 
+def curve64():
+    from oracle import Oracle
+    w = synth.workload("cu64")
+    q, rho, _ = synth.make_microstructure(w)
+    o = Oracle(w.shape, q, rho)
+    reps = [o.increment(Loading(), tol=w.tol, max_iter=2000) for _ in range(3)]
+    idx = np.random.default_rng(64).choice(w.voxels, 64, replace=False)
+    return {"workload": "cu64", "curve": [r["Sigma"][2] for r in reps],
+            "Sigma": [list(r["Sigma"]) for r in reps], "iters": [r["iters"] for r in reps],
+            "E": [list(r["E"]) for r in reps], "tol": w.tol, "sample_index": idx.tolist(),
+            "sigma_sample": o.field("sigma")[:, idx].tolist(),
+            "strain_sample": o.field("strain")[:, idx].tolist(),
+            "rho_sample": o.field("rho")[idx].tolist()}
+
+
 if __name__ == "__main__":
-    with open(os.path.join(HERE, "adjoint_8cube.json"), "w") as fh:
-        json.dump(adjoint_case(), fh, indent=1)
-    with open(os.path.join(HERE, "curve_16cube.json"), "w") as fh:
-        json.dump(curve16(), fh, indent=1)
+    which = sys.argv[1:] or ["adjoint", "curve16"]
+    if "adjoint" in which:
+        with open(os.path.join(HERE, "adjoint_8cube.json"), "w") as fh:
+            json.dump(adjoint_case(), fh, indent=1)
+    if "curve16" in which:
+        with open(os.path.join(HERE, "curve_16cube.json"), "w") as fh:
+            json.dump(curve16(), fh, indent=1)
+    if "curve64" in which:
+        with open(os.path.join(HERE, "curve_64cube.json"), "w") as fh:
+            json.dump(curve64(), fh, indent=1)

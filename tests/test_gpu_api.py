@@ -1,0 +1,141 @@
+"""The C ABI on the GPU: error handling, snapshots, determinism, and parity
+for a non-integral rate exponent (the exp/log kernel variant)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Oracle, Flow, Loading
+
+pytestmark = pytest.mark.gpu
+
+
+def micro(shape, n_grains, seed):
+    g = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(4)]
+    grains = synth.voronoi_grains(shape, n_grains, g[0])
+    q = synth.random_quaternions(n_grains, g[1])
+    quat = np.moveaxis(q[grains], -1, 0).reshape(4, -1).copy()
+    rho = synth.lognormal_rho(shape, 1e12, 0.3, g[2]).reshape(-1)
+    return quat, rho
+
+
+def solver(shape=(16, 16, 16), precision="fp64", seed=21, material=None):
+    from paper_1509_04953_amd import Solver, Material, Load
+    quat, rho = micro(shape, 6, seed)
+    s = Solver(shape, precision)
+    s.set_material(material or Material())
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load())
+    return s, quat, rho
+
+
+def test_error_paths(require_gpu):
+    from paper_1509_04953_amd import Solver, Material, Load, Opts, FftevpError, EINVAL, ESTATE, NOT_CONVERGED
+    print("case: error paths", flush=True)
+    s = Solver((16, 16, 16))
+    with pytest.raises(FftevpError) as e:
+        s.step()
+    assert e.value.status == ESTATE
+    quat, rho = micro((16, 16, 16), 4, 3)
+    bad = quat.copy()
+    bad[:, 5] *= 1.01
+    s.set_material(Material())
+    with pytest.raises(FftevpError) as e:
+        s.set_microstructure(bad, rho)
+    assert e.value.status == EINVAL
+    r2 = rho.copy()
+    r2[7] = -1.0
+    with pytest.raises(FftevpError) as e:
+        s.set_microstructure(quat, r2)
+    assert e.value.status == EINVAL
+    r2[7] = np.nan
+    with pytest.raises(FftevpError) as e:
+        s.set_microstructure(quat, r2)
+    assert e.value.status == EINVAL
+    with pytest.raises(FftevpError) as e:
+        s.set_material(Material(C11=100.0, C12=120.0))
+    assert e.value.status == EINVAL
+    with pytest.raises(FftevpError) as e:
+        s.set_loading(Load(strain_ctrl=(0, 0, 0, 0, 0, 0)))
+    assert e.value.status == EINVAL
+    with pytest.raises(FftevpError) as e:
+        s.set_loading(Load(dt=0.0))
+    assert e.value.status == EINVAL
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load())
+    # max_iter reached: reported, state not committed
+    before = s.field("sigma").cpu().numpy().copy()
+    r = s.step(Opts(tol=1e-14, max_iter=3))
+    assert r.status == NOT_CONVERGED and r.iters == 3
+    assert np.array_equal(s.field("sigma").cpu().numpy(), before)
+    assert np.array_equal(s.field("epsp").cpu().numpy(), np.zeros_like(before))
+    # and the same increment then converges from the unchanged state
+    r = s.step(Opts(tol=1e-8))
+    assert r.status == 0
+    assert abs(r.E[2] + 2e-3) < 1e-15
+
+
+def test_snapshot_resume_is_bit_exact(require_gpu):
+    from paper_1509_04953_amd import Opts
+    print("case: snapshots", flush=True)
+    s, _, _ = solver()
+    o = Opts(tol=1e-8)
+    s.step(o)
+    snap = s.save_state()
+    ra = [s.step(o) for _ in range(2)]
+    fa = {k: s.field(k).cpu().numpy() for k in ("sigma", "strain", "epsp", "rho")}
+    s.load_state(snap)
+    rb = [s.step(o) for _ in range(2)]
+    fb = {k: s.field(k).cpu().numpy() for k in ("sigma", "strain", "epsp", "rho")}
+    for a, b in zip(ra, rb):
+        assert a.iters == b.iters and np.array_equal(a.Sigma, b.Sigma)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_two_runs_are_bitwise_identical(require_gpu):
+    from paper_1509_04953_amd import Opts
+    print("case: determinism", flush=True)
+    out = []
+    for _ in range(2):
+        s, _, _ = solver(shape=(32, 32, 16), precision="mixed")
+        for _ in range(2):
+            s.step(Opts(tol=1e-6))
+        out.append([s.field(k).cpu().numpy() for k in ("sigma", "strain", "rho")])
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_non_integral_exponent_matches_oracle(require_gpu):
+    from paper_1509_04953_amd import Material, Opts
+    print("case: n = 9.5", flush=True)
+    s, quat, rho = solver(material=Material(n=9.5))
+    o = Oracle((16, 16, 16), quat, rho, flow=Flow(n=9.5))
+    for _ in range(2):
+        r = s.step(Opts(tol=1e-11, max_iter=3000))
+        ro = o.increment(Loading(), tol=1e-11, max_iter=3000)
+        assert r.status == 0
+        assert abs(r.Sigma[2] - ro["Sigma"][2]) < 1e-10 * abs(ro["Sigma"][2])
+    for k in ("sigma", "strain", "epsp", "rho"):
+        g = s.field(k).cpu().numpy()
+        v = o.field(k)
+        assert np.abs(g - v).max() < 1e-10 * np.abs(v).max(), k
+
+
+def test_stress_controlled_shear_and_strain_controlled_all(require_gpu):
+    """Other loadings through the same boundary: all six components strain
+    controlled (simple shear rate), compared with the oracle."""
+    from paper_1509_04953_amd import Load, Opts
+    print("case: simple shear, all strain controlled", flush=True)
+    s, quat, rho = solver(shape=(16, 8, 16))
+    ld = Load(Edot=(0, 0, 0, 0, 0, 5e-4), strain_ctrl=(1, 1, 1, 1, 1, 1))
+    s.set_loading(ld)
+    o = Oracle((16, 8, 16), quat, rho)
+    lo = Loading(Edot=np.array(ld.Edot, float), strain_ctrl=np.ones(6, int))
+    for _ in range(2):
+        r = s.step(Opts(tol=1e-11, max_iter=3000))
+        ro = o.increment(lo, tol=1e-11, max_iter=3000)
+        assert r.status == 0
+    g = s.field("sigma").cpu().numpy()
+    v = o.field("sigma")
+    assert np.abs(g - v).max() < 1e-10 * np.abs(v).max()
