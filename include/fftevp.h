@@ -175,15 +175,17 @@ fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
                                        const double dL_dSigma_mean[6],
                                        void* adj_state_dev, double dL_dtheta[4]);
 
-/* Kernel timing (diagnostics). When enabled, every kernel the solver launches
- * is bracketed by HIP events on the context's stream, and the durations of
- * launches that did work (not those skipped after convergence) are summed per
- * kernel class: 0 local solve + x-FFTs, 1 reduction/stop test, 2 forward
- * y-FFT, 3 z-FFT + Green operator, 4 inverse y-FFT, 5 end-of-increment update,
- * 6 adjoint set-up. fftevp_get_profile copies the sums (ms) and launch counts
- * into caller arrays of FFTEVP_NPROF entries and, if reset != 0, clears them. */
+/* Kernel timing (diagnostics). Bit k of class_mask brackets every launch of
+ * kernel class k with HIP events on the context's stream: 0 local solve +
+ * x-FFTs, 1 (unused), 2 forward y-FFT + first reduction stage, 3 z-FFT +
+ * Green operator + stop test, 4 inverse y-FFT, 5 end-of-increment update,
+ * 6 adjoint set-up and reverse update. Durations of launches that did work
+ * (not those skipped after convergence) are summed per class.
+ * fftevp_get_profile copies the sums (ms) and launch counts into caller
+ * arrays of FFTEVP_NPROF entries and, if reset != 0, clears them. Each timed
+ * launch adds about 4 us of event overhead to the stream. */
 #define FFTEVP_NPROF 7
-fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int enable);
+fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int class_mask);
 fftevp_status fftevp_get_profile(fftevp_ctx* ctx, double* ms, long long* launches, int reset);
 
 const char* fftevp_status_string(fftevp_status status);

@@ -139,3 +139,28 @@ def test_curve_16cube_matches_golden(require_gpu):
         c.append(r.Sigma[2])
     c = np.array(c)
     assert np.abs(c - np.array(d["curve"])).max() < 1e-10 * np.abs(c).max()
+
+
+def test_curve_64cube_matches_golden(require_gpu):
+    """64^3, 100 grains, log-normal density, tol 1e-6: the oracle's first
+    three increments (stored by tests/golden/make_golden.py)."""
+    from paper_1509_04953_amd import Opts
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "curve_64cube.json")))
+    w = synth.workload("cu64")
+    s, _, _ = make(w, "fp64")
+    idx = np.array(d["sample_index"])
+    for inc in range(3):
+        print(f"case: 64^3 increment {inc}", flush=True)
+        r = s.step(Opts(tol=w.tol))
+        assert r.status == 0
+        assert r.iters == d["iters"][inc]
+        assert abs(r.Sigma[2] - d["curve"][inc]) < 1e-10 * abs(d["curve"][inc])
+        assert np.allclose(r.E, d["E"][inc], rtol=1e-10, atol=1e-15)
+    sig = s.field("sigma").cpu().numpy()[:, idx]
+    e = s.field("strain").cpu().numpy()[:, idx]
+    rho = s.field("rho").cpu().numpy()[idx]
+    ss = np.array(d["sigma_sample"])
+    assert np.abs(sig - ss).max() < 1e-10 * np.abs(ss).max()
+    es = np.array(d["strain_sample"])
+    assert np.abs(e - es).max() < 1e-10 * np.abs(es).max()
+    assert np.abs(rho - np.array(d["rho_sample"])).max() < 1e-10 * np.max(d["rho_sample"])
