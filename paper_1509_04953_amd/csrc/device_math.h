@@ -142,6 +142,74 @@ __device__ __forceinline__ T resolved(const T (&s)[6]) {
   return T(kUN) * tn + T(kUS) * ts;
 }
 
+// Structure of the 12 systems in the crystal frame, read off kSign. The
+// normal part of m_a is kUN * nsgn(a) * d_t with t = ntype(a) the normal slot
+// that is zero and d_0 = e1 - e2, d_1 = e0 - e2, d_2 = e0 - e1. The shear
+// part is kUS * ssgn(a) * (e_p + srho(a) e_q), where (p, q), p < q, are the
+// two shear slots other than t (the zero shear slot of every system is the
+// one of its normal type). Resolved shears, flow sums and the Jacobian are
+// assembled from the per-type sums these groupings allow.
+__host__ __device__ constexpr int ntype(int a) {
+  return kSign[a][0] == 0 ? 0 : (kSign[a][1] == 0 ? 1 : 2);
+}
+__host__ __device__ constexpr int nsgn(int a) { return ntype(a) == 0 ? kSign[a][1] : kSign[a][0]; }
+__host__ __device__ constexpr int slot_p(int t) { return t == 0 ? 1 : 0; }
+__host__ __device__ constexpr int slot_q(int t) { return t == 2 ? 1 : 2; }
+__host__ __device__ constexpr int ssgn(int a) { return kSign[a][3 + slot_p(ntype(a))]; }
+__host__ __device__ constexpr int srho(int a) {
+  return kSign[a][3 + slot_p(ntype(a))] * kSign[a][3 + slot_q(ntype(a))];
+}
+// d_t as a 3-vector: component i of d_t
+__host__ __device__ constexpr int dcomp(int t, int i) {
+  return i == t ? 0 : ((t == 0) ? (i == 1 ? 1 : -1) : (i == 0 ? 1 : -1));
+}
+// position of system a among the four systems of its type
+__host__ __device__ constexpr int tpos(int a) {
+  int k = 0;
+  for (int b = 0; b < a; ++b) k += ntype(b) == ntype(a);
+  return k;
+}
+__host__ __device__ constexpr bool structure_ok() {
+  for (int a = 0; a < 12; ++a) {
+    const int t = ntype(a);
+    for (int i = 0; i < 3; ++i)
+      if (kSign[a][i] != nsgn(a) * dcomp(t, i)) return false;
+    if (kSign[a][3 + t] != 0) return false;
+    if (kSign[a][3 + slot_p(t)] != ssgn(a)) return false;
+    if (kSign[a][3 + slot_q(t)] != ssgn(a) * srho(a)) return false;
+    if (ssgn(a) == 0 || srho(a) == 0) return false;
+  }
+  for (int t = 0; t < 3; ++t) {
+    int c = 0;
+    for (int a = 0; a < 12; ++a) c += ntype(a) == t;
+    if (c != 4) return false;
+  }
+  return true;
+}
+static_assert(structure_ok(), "slip-system sign table does not have the assumed structure");
+
+// Resolved shears x_a = m_a : s * (scale), a in type t: cn = kUN * scale,
+// cs = kUS * scale. One subtraction, two products, a sum and a difference
+// serve the four systems of the type.
+template <int TT, typename T>
+__device__ __forceinline__ void resolved_type(const T (&s)[6], T cn, T cs, T (&x)[4]) {
+  constexpr int P = slot_p(TT), Q = slot_q(TT);
+  const T dn = cn * (TT == 0 ? s[1] - s[2] : (TT == 1 ? s[0] - s[2] : s[0] - s[1]));
+  const T hp = cs * s[3 + P], hq = cs * s[3 + Q];
+  const T pp = hp + hq, pm = hp - hq;
+  static_for<0, 12>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    if constexpr (ntype(A) == TT) {
+      constexpr int j = tpos(A);
+      const T sh = srho(A) > 0 ? pp : pm;
+      if constexpr (nsgn(A) > 0 && ssgn(A) > 0) x[j] = dn + sh;
+      else if constexpr (nsgn(A) > 0) x[j] = dn - sh;
+      else if constexpr (ssgn(A) > 0) x[j] = sh - dn;
+      else x[j] = -(dn + sh);
+    }
+  });
+}
+
 // Flow at a crystal-frame stress s:
 //   w[a]  = |x_a|^(n-1),  x_a = tau_a / tauc
 //   g[k]  = sum_a sign(x_a)|x_a|^n kSign[a][k]   (epsdot_p = gdot0 * u_k g[k])
@@ -149,64 +217,81 @@ __device__ __forceinline__ T resolved(const T (&s)[6]) {
 //   asum  = sum_a |x_a|^n
 // INTN: n is a positive integer (n_int); the powers then come from a
 // binary-exponent loop with a uniform trip count. Otherwise
-// |x|^(n-1) = exp((n-1) log|x|). Systems are processed four at a time to
-// bound the number of live registers.
-template <bool INTN, int G, typename T, typename W>
-__device__ __forceinline__ void flow_group(const T (&s)[6], T itauc, T n, int n_int, W (&w)[12],
-                                           T (&g)[6], T& visc, T& asum) {
-  T x[4], wg[4];
-  static_for<0, 4>([&](auto ac) {
-    constexpr int A = decltype(ac)::value;
-    x[A] = resolved<4 * G + A>(s) * itauc;
-  });
+// |x|^(n-1) = exp((n-1) log|x|). The systems are processed one normal type
+// (four systems) at a time to bound the number of live registers.
+template <bool INTN, int TT, typename T, typename W>
+__device__ __forceinline__ void flow_type(const T (&s)[6], T cn, T cs, T n, int n_int, W (&w)[12],
+                                          T (&g)[6], T& visc, T& asum) {
+  T x[4], wg[4], ax[4];
+  resolved_type<TT>(s, cn, cs, x);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) ax[a] = fabs(x[a]);
   if constexpr (INTN) {
+    // |x|^(n-1) by binary powers: the lowest bit sets the start value
     T base[4];
+    int e = n_int - 1;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      base[a] = fabs(x[a]);
-      wg[a] = T(1);
+      base[a] = ax[a];
+      wg[a] = (e & 1) ? ax[a] : T(1);
     }
 #pragma unroll 1
-    for (int e = n_int - 1; e != 0; e >>= 1) {
+    for (e >>= 1; e != 0; e >>= 1) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) base[a] *= base[a];
       if (e & 1) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) wg[a] *= base[a];
       }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) base[a] *= base[a];
     }
   } else {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const T ax = fabs(x[a]);
-      wg[a] = ax > T(0) ? exp((n - T(1)) * log(ax)) : (n == T(1) ? T(1) : T(0));
-    }
+    for (int a = 0; a < 4; ++a)
+      wg[a] = ax[a] > T(0) ? exp((n - T(1)) * log(ax[a])) : (n == T(1) ? T(1) : T(0));
   }
-  static_for<0, 4>([&](auto ac) {
+  // signed |x|^n, grouped: gn = sum nsgn sp (normal part), gs[r] = sum ssgn sp
+  // over the systems with srho = +1 (r = 0) or -1 (r = 1)
+  T gn = T(-0.0), gs0 = T(-0.0), gs1 = T(-0.0);
+  static_for<0, 12>([&](auto ac) {
     constexpr int A = decltype(ac)::value;
-    const T ax = fabs(x[A]);
-    const T p = wg[A] * ax;
-    w[4 * G + A] = W(wg[A]);
-    visc += p * ax;
-    asum += p;
-    const T sp = x[A] < T(0) ? -p : p;
-    static_for<0, 6>([&](auto kc) {
-      constexpr int K = decltype(kc)::value;
-      acc_sign<kSign[4 * G + A][K]>(g[K], sp);
-    });
+    if constexpr (ntype(A) == TT) {
+      constexpr int j = tpos(A);
+      const T p = wg[j] * ax[j];
+      w[A] = W(wg[j]);
+      visc += p * ax[j];
+      asum += p;
+      const T sp = x[j] < T(0) ? -p : p;
+      if constexpr (nsgn(A) > 0) gn += sp;
+      else gn -= sp;
+      if constexpr (srho(A) > 0) {
+        if constexpr (ssgn(A) > 0) gs0 += sp;
+        else gs0 -= sp;
+      } else {
+        if constexpr (ssgn(A) > 0) gs1 += sp;
+        else gs1 -= sp;
+      }
+    }
   });
+  static_for<0, 3>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    if constexpr (dcomp(TT, I) > 0) g[I] += gn;
+    else if constexpr (dcomp(TT, I) < 0) g[I] -= gn;
+  });
+  g[3 + slot_p(TT)] += gs0 + gs1;
+  g[3 + slot_q(TT)] += gs0 - gs1;
 }
 
 template <bool INTN, typename T, typename W>
 __device__ __forceinline__ void flow_eval(const T (&s)[6], T itauc, T n, int n_int, W (&w)[12],
                                           T (&g)[6], T& visc, T& asum) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = T(0);
-  visc = T(0);
-  asum = T(0);
-  flow_group<INTN, 0>(s, itauc, n, n_int, w, g, visc, asum);
-  flow_group<INTN, 1>(s, itauc, n, n_int, w, g, visc, asum);
-  flow_group<INTN, 2>(s, itauc, n, n_int, w, g, visc, asum);
+  for (int k = 0; k < 6; ++k) g[k] = T(-0.0);
+  visc = T(-0.0);
+  asum = T(-0.0);
+  const T cn = T(kUN) * itauc, cs = T(kUS) * itauc;
+  flow_type<INTN, 0>(s, cn, cs, n, n_int, w, g, visc, asum);
+  flow_type<INTN, 1>(s, cn, cs, n, n_int, w, g, visc, asum);
+  flow_type<INTN, 2>(s, cn, cs, n, n_int, w, g, visc, asum);
 }
 
 // cubic-form 6x6 (Mandel) times vector: normal block (d, o), shear diag s
@@ -245,27 +330,80 @@ __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], co
 }
 
 // J = A + cj * sum_a w_a m_a m_a^T  (packed lower triangle, 21 entries),
-// assembled entry by entry in precision JT.
+// assembled in precision JT from per-type sums of the weights:
+//   wp[t][r] = sum of w_a over type t with srho = +1 (r = 0) / -1 (r = 1),
+//   v[t][r]  = the same sums of nsgn ssgn w_a.
+// Normal block: (d_t d_t^T) (wp0 + wp1) / 6; shear block: on the pair (p, q)
+// of type t, diagonal wp0 + wp1 and off-diagonal wp0 - wp1, times 1/12;
+// mixed block: d_t (x) (e_p (v0 + v1) + e_q (v0 - v1)) kUN kUS.
 template <typename JT, typename T>
 __device__ __forceinline__ void local_jacobian(const Mat& M, const T (&w)[12], T cj, JT (&J)[21]) {
-  // T: type of the weights and of the assembly
-  static_for<0, 6>([&](auto ic) {
+  JT wd[3], wo[3], vp[3], vm[3];
+  static_for<0, 3>([&](auto tc) {
+    constexpr int TT = decltype(tc)::value;
+    JT w0 = JT(-0.0), w1 = JT(-0.0), v0 = JT(-0.0), v1 = JT(-0.0);
+    static_for<0, 12>([&](auto ac) {
+      constexpr int A = decltype(ac)::value;
+      if constexpr (ntype(A) == TT) {
+        const JT x = JT(w[A]);
+        if constexpr (srho(A) > 0) {
+          w0 += x;
+          if constexpr (nsgn(A) * ssgn(A) > 0) v0 += x;
+          else v0 -= x;
+        } else {
+          w1 += x;
+          if constexpr (nsgn(A) * ssgn(A) > 0) v1 += x;
+          else v1 -= x;
+        }
+      }
+    });
+    wd[TT] = w0 + w1;
+    wo[TT] = w0 - w1;
+    vp[TT] = v0 + v1;
+    vm[TT] = v0 - v1;
+  });
+  const JT fn = JT(cj) * JT(1.0 / 6.0), fs = JT(cj) * JT(1.0 / 12.0), fm = JT(cj) * JT(kUN * kUS);
+  const JT ad = JT(M.a_d), ao = JT(M.a_o), as = JT(M.a_s);
+  // normal block: (i, i) = sum of wd over the two types with d_t[i] != 0,
+  // (i, k) = -wd of the third type
+  J[tri(0, 0)] = ad + fn * (wd[1] + wd[2]);
+  J[tri(1, 1)] = ad + fn * (wd[0] + wd[2]);
+  J[tri(2, 2)] = ad + fn * (wd[0] + wd[1]);
+  J[tri(1, 0)] = ao - fn * wd[2];
+  J[tri(2, 0)] = ao - fn * wd[1];
+  J[tri(2, 1)] = ao - fn * wd[0];
+  // shear block: slot j lies in the pairs of the two types t != j
+  J[tri(3, 3)] = as + fs * (wd[1] + wd[2]);
+  J[tri(4, 4)] = as + fs * (wd[0] + wd[2]);
+  J[tri(5, 5)] = as + fs * (wd[0] + wd[1]);
+  static_for<0, 3>([&](auto tc) {
+    constexpr int TT = decltype(tc)::value;
+    J[tri(3 + slot_q(TT), 3 + slot_p(TT))] = fs * wo[TT];
+  });
+  // mixed block: entry (i, 3 + j) = sum over types t with d_t[i] != 0 and
+  // j in {p, q} of d_t[i] * (j == p ? vp : vm)
+  static_for<0, 3>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
-    static_for<0, I + 1>([&](auto jc) {
-      constexpr int J2 = decltype(jc)::value;
-      T h = T(0);
-      static_for<0, 12>([&](auto ac) {
-        constexpr int A = decltype(ac)::value;
-        acc_sign<kSign[A][I] * kSign[A][J2]>(h, w[A]);
+    static_for<0, 3>([&](auto jc) {
+      constexpr int J3 = decltype(jc)::value;
+      JT h = JT(-0.0);
+      static_for<0, 3>([&](auto tc) {
+        constexpr int TT = decltype(tc)::value;
+        if constexpr (dcomp(TT, I) != 0 && J3 != TT) {
+          const JT c = (J3 == slot_p(TT)) ? vp[TT] : vm[TT];
+          if constexpr (dcomp(TT, I) > 0) h += c;
+          else h -= c;
+        }
       });
-      constexpr double f = (I < 3 && J2 < 3) ? 1.0 / 6.0 : ((I >= 3 && J2 >= 3) ? 1.0 / 12.0 : kUN * kUS);
-      T a0 = T(0);
-      if constexpr (I < 3 && J2 < 3) a0 = (I == J2) ? T(M.a_d) : T(M.a_o);
-      else if constexpr (I == J2) a0 = T(M.a_s);
-      J[tri(I, J2)] = JT(a0 + cj * T(f) * h);
+      J[tri(3 + J3, I)] = fm * h;
     });
   });
 }
+
+// 1/d: the hardware reciprocal (1 ulp) for the FP32 Newton direction, a
+// correctly rounded division in FP64
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
 
 // Solve J x = rhs for SPD J (packed lower triangle) by J = L D L^T with unit
 // lower L. P holds L scaled by D column-wise (P_ij = L_ij d_j), id = 1/d.
@@ -277,7 +415,7 @@ __device__ __forceinline__ void ldl_solve(const T (&J)[21], const T (&rhs)[6], T
     T d = J[tri(j, j)];
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= P[tri(j, k)] * P[tri(j, k)] * id[k];
-    id[j] = T(1) / d;
+    id[j] = recip(d);
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       T v = J[tri(i, j)];

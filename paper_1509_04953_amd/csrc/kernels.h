@@ -16,6 +16,20 @@ enum { MODE_NEWTON = 0, MODE_TANGENT = 1, MODE_EXPORT = 2 };
 // [11] max Newton iterations (reduced by max)
 constexpr int NPART = 12;
 
+// Voxels per block of the local kernel (256 threads, several voxels each);
+// x-lines per block for a line length n0 (every power of two in [8, 512]
+// divides the planes n1 * n2 >= 64).
+#ifndef FFTEVP_LOCAL_VPB
+#define FFTEVP_LOCAL_VPB 256
+#endif
+static_assert(FFTEVP_LOCAL_VPB >= 256 && FFTEVP_LOCAL_VPB <= 512 &&
+                  (FFTEVP_LOCAL_VPB & (FFTEVP_LOCAL_VPB - 1)) == 0,
+              "local block size: a power of two in [256, 512] voxels");
+__host__ __device__ constexpr int local_lines_per_block(int n0) {
+  return n0 >= FFTEVP_LOCAL_VPB ? 1 : FFTEVP_LOCAL_VPB / n0;
+}
+
+
 // Device-resident control block of one increment.
 struct Ctl {
   double E[6];      // macroscopic strain (Mandel) used by the next spectral update

@@ -61,14 +61,54 @@ __device__ __forceinline__ void block_reduce(double (&v)[NP], double* __restrict
   }
 }
 
+// Block of 256 threads, reduction through LDS (scratch: NP * 288 doubles):
+// every thread stores its NP values; 16 threads per value combine 16 entries
+// each (thread c takes entries c, c + 16, ...); one thread per value combines
+// those 16 results. The last NMAX values are reduced by max. Fixed order.
+template <int NP, int NMAX>
+__device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], double* red,
+                                                 double* __restrict__ out, size_t stride) {
+  constexpr int RS = 272;  // row stride: rows of adjacent values fall on other banks
+  double* red2 = red + NP * RS;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) red[k * RS + t] = v[k];
+  __syncthreads();
+  if (t < NP * 16) {
+    const int k = t >> 4, c = t & 15;
+    const double* row = red + k * RS + c;
+    double r = row[0];
+    if (k >= NP - NMAX) {
+#pragma unroll
+      for (int i = 1; i < 16; ++i) r = fmax(r, row[16 * i]);
+    } else {
+#pragma unroll
+      for (int i = 1; i < 16; ++i) r += row[16 * i];
+    }
+    red2[t] = r;
+  }
+  __syncthreads();
+  if (t < NP) {
+    double r = red2[16 * t];
+    if (t >= NP - NMAX) {
+#pragma unroll
+      for (int i = 1; i < 16; ++i) r = fmax(r, red2[16 * t + i]);
+    } else {
+#pragma unroll
+      for (int i = 1; i < 16; ++i) r += red2[16 * t + i];
+    }
+    out[t * stride] = r;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // local kernel
 // ---------------------------------------------------------------------------
 template <typename T, int N0>
 struct LocalShape {
   static constexpr int NT = 256;
-  static constexpr int LPB = N0 >= NT ? 1 : NT / N0;   // x-lines per block
-  static constexpr int VPT = N0 > NT ? N0 / NT : 1;    // voxels per thread
+  static constexpr int LPB = local_lines_per_block(N0);  // x-lines per block
+  static constexpr int VPT = LPB * N0 / NT;              // voxels per thread
   static constexpr int LS = N0 + 1;                    // LDS line stride
   static constexpr int H = N0 / 2;
 };
@@ -121,7 +161,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
     LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
   if (a.ctl && a.ctl->done) return;
-  __shared__ cx<T> sh[3 * S::LPB * S::LS];
+  // LDS: the six strain/polarisation lines (complex pairs), later reused by
+  // the block reduction
+  constexpr int SH_BYTES = 3 * S::LPB * S::LS * (int)sizeof(cx<T>);
+  constexpr int RED_BYTES = NPART * 288 * (int)sizeof(double);
+  __shared__ __align__(16) unsigned char lds[SH_BYTES > RED_BYTES ? SH_BYTES : RED_BYTES];
+  cx<T>* sh = reinterpret_cast<cx<T>*>(lds);
   const size_t planes = (size_t)a.n1 * a.n2;
   const size_t vox = planes * N0;
   const size_t line0 = (size_t)blockIdx.x * S::LPB;
@@ -356,7 +401,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
 #pragma unroll
     for (int k = 0; k < 6; ++k) a.e_nyq_next[(line0 + l) * 6 + k] = s * en[k];
   }
-  block_reduce<NPART, 1>(part, a.partial + blockIdx.x, gridDim.x);
+  __syncthreads();  // the line buffer is reused below
+  block_reduce_lds<NPART, 1>(part, reinterpret_cast<double*>(lds), a.partial + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -847,8 +893,7 @@ hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 int local_blocks(int n0, int n1, int n2) {
-  const int lpb = n0 >= 256 ? 1 : 256 / n0;
-  return n1 * n2 / lpb;
+  return n1 * n2 / local_lines_per_block(n0);
 }
 
 // number of x-frequency tiles of a y pass (= blocks in its reduction row)
