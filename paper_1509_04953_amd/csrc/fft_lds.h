@@ -89,20 +89,25 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
 }
 
 // One Stockham stage over LINES lines of length N (line stride LS, unit
-// element stride) with NT cooperating threads.
+// element stride) with NT cooperating threads. Thread order: line-major
+// (consecutive threads take the same butterfly of consecutive lines, so with
+// an odd line stride their LDS accesses spread over the banks in every
+// stage) for FP64 and for many lines; butterfly-major (unit-stride reads,
+// R-strided writes) for a few FP32 lines, where it measured faster.
 template <typename T, int N, int R, int NS, bool INV, int LINES, int LS, int NT>
 __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
                                                const cx<T>* __restrict__ tw) {
   constexpr int BF = N / R;
   constexpr int TOTAL = LINES * BF;
   constexpr int PER = (TOTAL + NT - 1) / NT;
+  constexpr bool LM = sizeof(T) == 8 || LINES >= 32;
   cx<T> v[PER][R];
   const int tid = threadIdx.x;
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int idx = tid + b * NT;
     if ((TOTAL % NT) == 0 || idx < TOTAL) {
-      const int line = idx / BF, j = idx % BF;
+      const int line = LM ? idx % LINES : idx / BF, j = LM ? idx / LINES : idx % BF;
       const cx<T>* src = buf + line * LS + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[r * BF];
@@ -113,7 +118,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
   for (int b = 0; b < PER; ++b) {
     const int idx = tid + b * NT;
     if ((TOTAL % NT) == 0 || idx < TOTAL) {
-      const int line = idx / BF, j = idx % BF;
+      const int line = LM ? idx % LINES : idx / BF, j = LM ? idx / LINES : idx % BF;
       const int k = j % NS;
       if constexpr (NS > 1) {
 #pragma unroll

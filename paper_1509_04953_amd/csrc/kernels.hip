@@ -172,6 +172,23 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
   const size_t line0 = (size_t)blockIdx.x * S::LPB;
   const Mat& M = a.m;
 
+  // per-voxel inputs of the thread's first voxel, requested before the x-FFT
+  // so that their latency overlaps it (later voxels load in the loop)
+  T pq[4], plam[6], pep[6], prho;
+  auto fetch = [&](size_t g) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pq[k] = a.quat[(size_t)k * vox + g];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) plam[k] = a.lam[(size_t)k * vox + g];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pep[k] = a.epsp[(size_t)k * vox + g];
+    prho = a.rho[g];
+  };
+  if constexpr (MODE != MODE_EXPORT) {
+    const int l = threadIdx.x / N0, x = threadIdx.x - (threadIdx.x / N0) * N0;
+    fetch((line0 + l) * N0 + x);
+  }
+
   load_packed<T, N0>(a.e_main, a.e_nyq, line0, sh);
   __syncthreads();
   fft_lines<T, N0, true, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
@@ -220,22 +237,21 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
       }
     };
     auto rot = [&](T (&R)[9]) { quat_rot(a.quat[g], a.quat[vox + g], a.quat[2 * vox + g], a.quat[3 * vox + g], R); };
-    const T tauc = T(M.tau0) + T(M.taylor) * sqrt(a.rho[g]);
+    if (v > 0) fetch(g);
+    const T tauc = T(M.tau0) + T(M.taylor) * sqrt(prho);
     const T itauc = T(1) / tauc;
 
     // b = C0^-1 lam + e - epsp in the crystal frame; start from lam
     T b[6], sc[6];
     {
-      T R[9], e[6], lam[6], bs[6];
-      rot(R);
+      T R[9], e[6], bs[6];
+      quat_rot(pq[0], pq[1], pq[2], pq[3], R);
       load_e(e);
+      cubic_mul(ci_d, ci_o, ci_s, plam, bs);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) lam[k] = a.lam[(size_t)k * vox + g];
-      cubic_mul(ci_d, ci_o, ci_s, lam, bs);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) bs[k] += e[k] - a.epsp[(size_t)k * vox + g];
+      for (int k = 0; k < 6; ++k) bs[k] += e[k] - pep[k];
       to_crystal(R, bs, b);
-      if constexpr (MODE == MODE_NEWTON) to_crystal(R, lam, sc);
+      if constexpr (MODE == MODE_NEWTON) to_crystal(R, plam, sc);
     }
 
     int nit = 0, fail = 0, nls = 0;
@@ -411,7 +427,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
 // LDS budget of the y and z passes; the tile width TX (x-frequencies per
 // block, six components each) is the largest power of two that fits.
 #ifndef FFTEVP_SPEC_LDS_KB
-#define FFTEVP_SPEC_LDS_KB 50
+#define FFTEVP_SPEC_LDS_KB 25
 #endif
 #ifndef FFTEVP_Y_LDS_KB
 #define FFTEVP_Y_LDS_KB 25
