@@ -444,6 +444,21 @@ __host__ __device__ constexpr int y_tile(int n) {
   return spec_tile<T>(n, FFTEVP_Y_LDS_KB);
 }
 
+// Workgroups are dealt round-robin to the eight XCDs, each with its own L2.
+// The y and z passes renumber them so that every XCD takes a contiguous range
+// of tiles: neighbouring tiles, whose rows share cache lines, then meet in
+// the same L2 instead of fetching those lines twice.
+#ifndef FFTEVP_XCD_REMAP
+#define FFTEVP_XCD_REMAP 1
+#endif
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  const int nx = gridDim.x, total = gridDim.x * gridDim.y;
+  int id = blockIdx.x + nx * blockIdx.y;
+  if (FFTEVP_XCD_REMAP && total % 8 == 0) id = (id % 8) * (total / 8) + id / 8;
+  bx = id % nx;
+  by = id / nx;
+}
+
 // Rows of W = 6 TX contiguous complex values (row stride rs) <-> W lines of
 // length N in LDS (line stride N + 1).
 template <typename T, int N, int W>
@@ -468,11 +483,13 @@ __device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict
 template <typename T, int N1, int TX, bool INV>
 __global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
   if (a.ctl && a.ctl->done) return;
+  int bx, by;
+  xcd_tile(bx, by);
   if constexpr (!INV) {
-    if (blockIdx.y == 0) {
+    if (by == 0) {
       const int ns = gridDim.x, nb = a.nb_local;
       const int chunk = (nb + ns - 1) / ns;
-      const int b0 = blockIdx.x * chunk, b1 = min(nb, b0 + chunk);
+      const int b0 = bx * chunk, b1 = min(nb, b0 + chunk);
       double v[NPART];
 #pragma unroll
       for (int k = 0; k < NPART; ++k) v[k] = 0.0;
@@ -481,15 +498,15 @@ __global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
         for (int k = 0; k < NPART - 1; ++k) v[k] += a.partial[(size_t)k * nb + b];
         v[NPART - 1] = fmax(v[NPART - 1], a.partial[(size_t)(NPART - 1) * nb + b]);
       }
-      block_reduce<NPART, 1>(v, a.stage1 + blockIdx.x, ns);
+      block_reduce<NPART, 1>(v, a.stage1 + bx, ns);
       return;
     }
   }
   constexpr int W = 6 * TX;
   __shared__ cx<T> sh[W * (N1 + 1)];
   const size_t rs = (size_t)a.h * 6;  // y stride
-  const size_t z = INV ? blockIdx.y : blockIdx.y - 1;
-  const size_t base = z * N1 * rs + (size_t)blockIdx.x * W;
+  const size_t z = INV ? by : by - 1;
+  const size_t base = z * N1 * rs + (size_t)bx * W;
   rows_to_lines<T, N1, W>(a.src + base, rs, sh);
   __syncthreads();
   fft_lines<T, N1, INV, W, N1 + 1, 256>(sh, a.tw);
@@ -530,9 +547,11 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
   constexpr int W = 6 * TX;
   __shared__ cx<T> sh[W * LS];
   __shared__ double E_sh[6];
+  int bx, by;
+  xcd_tile(bx, by);
   // the block holding xi = 0 finishes the reduction, tests for convergence
   // and updates the macroscopic strain before using it
-  if (blockIdx.x == 0 && blockIdx.y == 0) {
+  if (bx == 0 && by == 0) {
     __shared__ double tot[NPART];
     if (threadIdx.x < NPART) {
       const int k = threadIdx.x;
@@ -551,7 +570,7 @@ __global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
     __syncthreads();
   }
   const int H = a.h, n1 = a.n1;
-  const int ky = blockIdx.y, kx0 = blockIdx.x * TX;
+  const int ky = by, kx0 = bx * TX;
   const size_t zs = (size_t)n1 * H * 6;  // z stride
   cx<T>* __restrict__ buf = a.buf + ((size_t)ky * H + kx0) * 6;
   rows_to_lines<T, N2, W>(buf, zs, sh);
