@@ -236,7 +236,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
         for (int k = 0; k < 6; ++k) e[k] += T(a.dE[k]);
       }
     };
-    auto rot = [&](T (&R)[9]) { quat_rot(a.quat[g], a.quat[vox + g], a.quat[2 * vox + g], a.quat[3 * vox + g], R); };
     if (v > 0) fetch(g);
     const T tauc = T(M.tau0) + T(M.taylor) * sqrt(prho);
     const T itauc = T(1) / tauc;
@@ -338,7 +337,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
       fail = conv ? 0 : 1;
     } else {  // MODE_TANGENT: linear solve with the tangent at the given stress
       T R[9], st[6], stc[6], w[12], g6[6], visc, asum, J[21];  // full precision tangent
-      rot(R);
+      quat_rot(pq[0], pq[1], pq[2], pq[3], R);
 #pragma unroll
       for (int k = 0; k < 6; ++k) st[k] = a.sig_t[(size_t)k * vox + g];
       to_crystal(R, st, stc);
@@ -352,12 +351,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
     T sig[6], err[6], e[6];
     {
       T R[9], dsl[6];
-      rot(R);
+      quat_rot(pq[0], pq[1], pq[2], pq[3], R);
       to_sample(R, sc, sig);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) dsl[k] = sig[k] - a.lam[(size_t)k * vox + g];
+      for (int k = 0; k < 6; ++k) dsl[k] = sig[k] - plam[k];
       cubic_mul(ci_d, ci_o, ci_s, dsl, err);
     }
+    // re-read e from LDS rather than keeping it live through the Newton loop
+    asm volatile("" ::: "memory");
     load_e(e);
     T tr = T(0), eps[6], tau[6];
 #pragma unroll
