@@ -152,6 +152,24 @@ def stored_traffic(kernel, precision):
     return None
 
 
+def stored_valu_issue_us(kernel, precision):
+    """VALU issue time per launch (us) from the committed shader-counter
+    summary: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz); None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "fftevp_128cube_sq_counters.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    src = source_hash()
+    for ln in lines:
+        f = ln.split()
+        if len(f) >= 3 and f[0] == "valu" and f[1] == kernel and f[2] == precision:
+            kv = dict(x.split("=", 1) for x in f[3:])
+            return float(kv["issue_us"]) if kv.get("sources") == src else None
+    return None
+
+
 def roofline(w, res, word):
     """Roofline of the local kernel (the dominant one) from the timed region;
     per-kernel averages from the fully timed follow-up increments."""
@@ -166,14 +184,18 @@ def roofline(w, res, word):
     share = {k: pa[k][0] for k in by}
     dom = max(share, key=share.get)
     prec = "fp64" if word == 8 else "mixed"
+    issue = stored_valu_issue_us("k_local", prec) if w.shape == (128, 128, 128) else None
     return {"kernel": "local", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": stored_traffic("k_local", prec),
+            "traffic": stored_traffic("k_local", prec) if w.shape == (128, 128, 128) else None,
             "bytes_per_launch": by["local"], "avg_ms": avg, "launches": n,
-            "largest_share": dom}, per_kernel
+            "largest_share": dom,
+            # the local kernel is limited by its vector-ALU issue rate: the
+            # profiled VALU issue time over this run's average launch time
+            "valu_issue_frac": (issue * 1e-3 / avg) if issue else None}, per_kernel
 
 
-def cpu_baseline(w, quat, rho, frac=16):
+def cpu_baseline(w, quat, rho, frac=4):
     """The oracle on a bounded sample of the same workload.
 
     Sample: the first two fixed-point iterations of the first increment;
