@@ -122,28 +122,43 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
                                             size_t line0, cx<T>* sh) {
   using S = LocalShape<T, N0>;
   constexpr int PER_LINE = S::H + 1;
-  // spectra are [line][k][component]: thread idx takes pair p of (l, k)
-  for (int idx = threadIdx.x; idx < 3 * S::LPB * PER_LINE; idx += S::NT) {
-    const int l = idx / (3 * PER_LINE);
-    const int rem = idx - l * (3 * PER_LINE);
-    const int k = rem / 3, p = rem - (rem / 3) * 3;
-    const size_t line = line0 + l;
-    cx<T> xa, xb;
-    if (k < S::H) {
-      const cx<T>* src = main + (line * S::H + k) * 6 + 2 * p;
-      xa = src[0];
-      xb = src[1];
-      if (k == 0) {
-        xa.y = T(0);
-        xb.y = T(0);
+  // spectra are [line][k][component]: thread idx takes pair p of (l, k).
+  // All loads of the thread are issued before the first LDS store.
+  constexpr int TOT = 3 * S::LPB * PER_LINE, PER = (TOT + S::NT - 1) / S::NT;
+  cx<T> xa[PER], xb[PER];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + b * S::NT;
+    if (idx < TOT) {
+      const int l = idx / (3 * PER_LINE);
+      const int rem = idx - l * (3 * PER_LINE);
+      const int k = rem / 3, p = rem - (rem / 3) * 3;
+      const size_t line = line0 + l;
+      if (k < S::H) {
+        const cx<T>* src = main + (line * S::H + k) * 6 + 2 * p;
+        xa[b] = src[0];
+        xb[b] = src[1];
+      } else {
+        xa[b] = {nyq[line * 6 + 2 * p], T(0)};
+        xb[b] = {nyq[line * 6 + 2 * p + 1], T(0)};
       }
-    } else {
-      xa = {nyq[line * 6 + 2 * p], T(0)};
-      xb = {nyq[line * 6 + 2 * p + 1], T(0)};
     }
-    cx<T>* Z = sh + (p * S::LPB + l) * S::LS;
-    Z[k] = {xa.x - xb.y, xa.y + xb.x};
-    if (k > 0 && k < S::H) Z[N0 - k] = {xa.x + xb.y, xb.x - xa.y};
+  }
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + b * S::NT;
+    if (idx < TOT) {
+      const int l = idx / (3 * PER_LINE);
+      const int rem = idx - l * (3 * PER_LINE);
+      const int k = rem / 3, p = rem - (rem / 3) * 3;
+      if (k == 0) {
+        xa[b].y = T(0);
+        xb[b].y = T(0);
+      }
+      cx<T>* Z = sh + (p * S::LPB + l) * S::LS;
+      Z[k] = {xa[b].x - xb[b].y, xa[b].y + xb[b].x};
+      if (k > 0 && k < S::H) Z[N0 - k] = {xa[b].x + xb[b].y, xb[b].x - xa[b].y};
+    }
   }
 }
 
@@ -391,7 +406,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
   fft_lines<T, N0, false, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
 
   // unpack: Xa[k] = (Z[k] + conj Z[N-k]) / 2, Xb[k] = (Z[k] - conj Z[N-k]) / 2i
-  for (int idx = threadIdx.x; idx < 3 * S::LPB * S::H; idx += S::NT) {
+  constexpr int UPER = (3 * S::LPB * S::H + S::NT - 1) / S::NT;
+#pragma unroll
+  for (int ub = 0; ub < UPER; ++ub) {
+    const int idx = threadIdx.x + ub * S::NT;
+    if (idx >= 3 * S::LPB * S::H) break;
     const int l = idx / (3 * S::H);
     const int rem = idx - l * (3 * S::H);
     const int k = rem / 3, p = rem - (rem / 3) * 3;
@@ -464,16 +483,46 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // length N in LDS (line stride N + 1).
 template <typename T, int N, int W>
 __device__ __forceinline__ void rows_to_lines(const cx<T>* __restrict__ src, size_t rs, cx<T>* sh) {
-  for (int idx = threadIdx.x; idx < N * W; idx += 256) {
-    const int r = idx / W, w = idx - (idx / W) * W;
-    sh[w * (N + 1) + r] = src[(size_t)r * rs + w];
+  // every load of the thread is issued before the first LDS store, so the
+  // HBM latencies overlap instead of adding up
+  constexpr int TOT = N * W, PER = (TOT + 255) / 256;
+  cx<T> v[PER];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + 256 * b;
+    if (TOT % 256 == 0 || idx < TOT) {
+      const int r = idx / W, w = idx - (idx / W) * W;
+      v[b] = src[(size_t)r * rs + w];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + 256 * b;
+    if (TOT % 256 == 0 || idx < TOT) {
+      const int r = idx / W, w = idx - (idx / W) * W;
+      sh[w * (N + 1) + r] = v[b];
+    }
   }
 }
 template <typename T, int N, int W>
 __device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict__ dst, size_t rs) {
-  for (int idx = threadIdx.x; idx < N * W; idx += 256) {
-    const int r = idx / W, w = idx - (idx / W) * W;
-    dst[(size_t)r * rs + w] = sh[w * (N + 1) + r];
+  constexpr int TOT = N * W, PER = (TOT + 255) / 256;
+  cx<T> v[PER];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + 256 * b;
+    if (TOT % 256 == 0 || idx < TOT) {
+      const int r = idx / W, w = idx - (idx / W) * W;
+      v[b] = sh[w * (N + 1) + r];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + 256 * b;
+    if (TOT % 256 == 0 || idx < TOT) {
+      const int r = idx / W, w = idx - (idx / W) * W;
+      dst[(size_t)r * rs + w] = v[b];
+    }
   }
 }
 
@@ -481,8 +530,13 @@ __device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict
 // extra row of blocks (blockIdx.y == 0): block b of that row reduces a
 // contiguous share of the local kernel's per-block partial sums, in a fixed
 // order, while the other rows transform.
+// waves per SIMD the y and z passes are compiled for (register budget)
+#ifndef FFTEVP_SPEC_WAVES
+#define FFTEVP_SPEC_WAVES 1
+#endif
+
 template <typename T, int N1, int TX, bool INV>
-__global__ __launch_bounds__(256) void k_ypass(YArgs<T> a) {
+__global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_ypass(YArgs<T> a) {
   if (a.ctl && a.ctl->done) return;
   int bx, by;
   xcd_tile(bx, by);
@@ -542,7 +596,7 @@ __device__ __forceinline__ void apply_gamma(cx<T> (&t)[6], T nx, T ny, T nz, T c
 }
 
 template <typename T, int N2, int TX>
-__global__ __launch_bounds__(256) void k_zgamma(ZArgs<T> a) {
+__global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zgamma(ZArgs<T> a) {
   if (a.ctl->done) return;
   constexpr int LS = N2 + 1;
   constexpr int W = 6 * TX;
