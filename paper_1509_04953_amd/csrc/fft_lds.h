@@ -102,7 +102,10 @@ __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
   constexpr int PER = (TOTAL + NT - 1) / NT;
   constexpr bool LM = sizeof(T) == 8 || LINES >= 32;
   cx<T> v[PER][R];
+  cx<T> wt[PER][R > 1 && NS > 1 ? R - 1 : 1];
   const int tid = threadIdx.x;
+  // inputs and twiddles are requested before the barrier, so the twiddle
+  // loads (cached table) overlap the wait for the other waves
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int idx = tid + b * NT;
@@ -111,6 +114,11 @@ __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
       const cx<T>* src = buf + line * LS + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[r * BF];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) wt[b][r - 1] = tw[k * r * (N / (NS * R))];
+      }
     }
   }
   __syncthreads();
@@ -122,10 +130,8 @@ __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
       const int k = j % NS;
       if constexpr (NS > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cx<T> w = tw[k * r * (N / (NS * R))];
-          v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
-        }
+        for (int r = 1; r < R; ++r)
+          v[b][r] = INV ? cmulc(v[b][r], wt[b][r - 1]) : cmul(v[b][r], wt[b][r - 1]);
       }
       dftR<T, R, INV>(v[b]);
       cx<T>* dst = buf + line * LS + (j / NS) * NS * R + k;
