@@ -81,11 +81,53 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
   v[7] = e[3] - o3;
 }
 
+// o * exp(-+ 2 pi i k / 16) for a compile-time k in [1, 8)
+template <typename T, bool INV, int K>
+__device__ __forceinline__ cx<T> w16(cx<T> o) {
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+  constexpr double h = 0.70710678118654752440;
+  if constexpr (K == 4) {
+    return rot90<T, INV>(o);
+  } else if constexpr (K == 2 || K == 6) {
+    // (1 -+ i) h or (-1 -+ i) h
+    const T a = T(h) * (o.x + (INV ? -o.y : o.y)), b = T(h) * (o.y - (INV ? -o.x : o.x));
+    if constexpr (K == 2) return {a, b};
+    else return INV ? cx<T>{-b, a} : cx<T>{b, -a};  // times -+ i
+  } else {
+    constexpr double cr = K == 1 ? c1 : (K == 3 ? s1 : (K == 5 ? -s1 : -c1));
+    constexpr double ci = K == 1 ? -s1 : (K == 3 ? -c1 : (K == 5 ? -c1 : -s1));
+    const cx<T> w = {T(cr), T(INV ? -ci : ci)};
+    return cmul(o, w);
+  }
+}
+
+// 16-point DFT: two 8-point DFTs of the even and odd elements and one
+// radix-2 combination with the 16th roots of unity.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  cx<T> e[8], o[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    e[k] = v[2 * k];
+    o[k] = v[2 * k + 1];
+  }
+  dft8<T, INV>(e);
+  dft8<T, INV>(o);
+  const cx<T> t[8] = {o[0], w16<T, INV, 1>(o[1]), w16<T, INV, 2>(o[2]), w16<T, INV, 3>(o[3]),
+                      w16<T, INV, 4>(o[4]), w16<T, INV, 5>(o[5]), w16<T, INV, 6>(o[6]), w16<T, INV, 7>(o[7])};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[k] = e[k] + t[k];
+    v[k + 8] = e[k] - t[k];
+  }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftR(cx<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
-  else dft8<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else dft16<T, INV>(v);
 }
 
 // One Stockham stage over LINES lines of length N (line stride LS, unit
@@ -145,9 +187,12 @@ __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
 template <typename T, int N, int NS, bool INV, int LINES, int LS, int NT>
 __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw) {
   if constexpr (NS < N) {
-    // radix plan: 8s first, then a final 4 or 2 (16 -> 4x4, 128 -> 8x4x4)
+    // radix plan: 16 where it leaves a factor of at least 8 (or is the whole
+    // transform), else 8s, then a final 4 or 2:
+    // 16 -> 16, 32 -> 8x4, 64 -> 8x8, 128 -> 16x8, 256 -> 16x16, 512 -> 8x8x8
     constexpr int REM = N / NS;
-    constexpr int R = (REM % 8 == 0 && REM != 16) ? 8 : (REM % 4 == 0 ? 4 : 2);
+    constexpr int R = (REM == 16 || REM == 128 || REM == 256) ? 16
+                      : (REM % 8 == 0 ? 8 : (REM % 4 == 0 ? 4 : 2));
     stockham_stage<T, N, R, NS, INV, LINES, LS, NT>(buf, tw);
     fft_rest<T, N, NS * R, INV, LINES, LS, NT>(buf, tw);
   }

@@ -60,7 +60,13 @@ def test_first_iterate_matches_local_solve(require_gpu):
     np.testing.assert_allclose(rep.Sigma, orep["Sigma"], rtol=1e-11, atol=1e-9)
 
 
-@pytest.mark.parametrize("shape,k", [((16, 16, 16), 3), ((32, 8, 16), 4), ((8, 32, 16), 2)])
+# every line length the transforms support along each axis (radix plans
+# 8, 16, 8x4, 8x8, 16x8, 16x16, 8x8x8; 512 voxels per x-line takes the
+# local kernel's two-voxels-per-thread path)
+@pytest.mark.parametrize("shape,k", [((16, 16, 16), 3), ((32, 8, 16), 4), ((8, 32, 16), 2),
+                                     ((8, 8, 8), 3), ((64, 16, 128), 2),
+                                     ((256, 8, 8), 3), ((8, 256, 8), 3), ((8, 8, 256), 3),
+                                     ((512, 8, 8), 3), ((8, 512, 8), 3), ((8, 8, 512), 3)])
 def test_iterates_match(require_gpu, shape, k):
     quat, rho = micro(shape, 6, 12)
     from paper_1509_04953_amd import Opts
