@@ -60,7 +60,8 @@ typedef enum {
   FFTEVP_FIELD_EPS_P = 2,       /* plastic strain, 6 comps                        */
   FFTEVP_FIELD_RHO = 3,         /* dislocation density, 1 comp                    */
   FFTEVP_FIELD_SIGMA_ITER = 4,  /* stress of the latest iteration, 6 comps        */
-  FFTEVP_FIELD_STRAIN_ITER = 5  /* compatible strain after the latest iteration   */
+  FFTEVP_FIELD_STRAIN_ITER = 5, /* compatible strain after the latest iteration   */
+  FFTEVP_FIELD_GDOT = 6         /* slip rates of the 12 systems, 1/s (see below)  */
 } fftevp_field;
 
 typedef struct fftevp_ctx fftevp_ctx;
@@ -147,7 +148,12 @@ fftevp_status fftevp_set_loading(fftevp_ctx* ctx, const fftevp_loading* loading)
  * some voxel Newton solves hit newton_max; state committed). out may be NULL. */
 fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_report* out);
 
-/* Copy a field (fftevp_field) into dst_dev (device, FP64, [ncomp][V]). */
+/* Copy a field (fftevp_field) into dst_dev (device, FP64, [ncomp][V]).
+ * FFTEVP_FIELD_GDOT: the flow rule (Eq. 2 with the power law above) evaluated
+ * at the committed stress and the current density, one rate per slip system
+ * in the order of the system list (planes (111), (-111), (1-11), (11-1),
+ * three <110> directions each), [12][V]; needs set_material and
+ * set_microstructure (ESTATE otherwise). */
 fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst_dev);
 
 /* Opaque device snapshot of the committed state (plastic strain, density,

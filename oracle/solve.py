@@ -191,6 +191,11 @@ class Oracle:
             return mandel_to_voigt(a.T)
         if name == "rho":
             return self.rho.copy()
+        if name == "gdot":
+            # flow rule (Eq. 2, power law of reading R1) at the committed stress
+            # and the current density, [12][V]
+            _, g = L.slip_rates(self.sigma, self.m, self.tauc(), self._gdot0(), self.flow.n)
+            return g.T.copy()
         raise KeyError(name)
 
 

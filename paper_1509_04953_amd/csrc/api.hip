@@ -795,6 +795,23 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
     case FFTEVP_FIELD_RHO: e = exp(ctx->b.rho, 1, 0); break;
     case FFTEVP_FIELD_SIGMA_ITER: e = exp(ctx->b.sig[ctx->sw], 6, 1); break;
     case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->e_last); break;
+    case FFTEVP_FIELD_GDOT: {
+      if (!ctx->have_mat || !ctx->have_micro)
+        return fail(ctx, FFTEVP_ESTATE, "set_material and set_microstructure must come first");
+      if (!ctx->state_ok)
+        return fail(ctx, FFTEVP_ESTATE, "an adjoint solve reused the state buffers: load a snapshot first");
+      Mat m{};
+      m.n = ctx->flow.n;
+      m.n_int = (std::floor(m.n) == m.n && m.n >= 1.0 && m.n <= 64.0) ? (int)m.n : 0;
+      m.tau0 = ctx->flow.tau0;
+      m.taylor = ctx->flow.alpha * ctx->flow.mu * ctx->flow.b;
+      const void* sg = ctx->b.sig[ctx->sc];
+      e = dbl ? launch_gdot<double>((const double*)sg, (const double*)ctx->b.quat, (const double*)ctx->b.rho, dst, V,
+                                    m, ctx->flow.gdot0, ctx->stream)
+              : launch_gdot<float>((const float*)sg, (const float*)ctx->b.quat, (const float*)ctx->b.rho, dst, V, m,
+                                   ctx->flow.gdot0, ctx->stream);
+      break;
+    }
     default: return fail(ctx, FFTEVP_EINVAL, "unknown field");
   }
   HIPCHK(e);

@@ -148,6 +148,9 @@ hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
 template <typename T>
+hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, size_t V, const Mat& m,
+                       double gdot0, hipStream_t s);
+template <typename T>
 hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
                          int nblocks, double* out2, hipStream_t s);
 template <typename T>

@@ -743,6 +743,38 @@ __global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
   block_reduce<2, 0>(part, a.partial + (size_t)blockIdx.x * 2);
 }
 
+// Slip rates gdot_a = gdot0 |tau_a / tauc|^n sign(tau_a) of the 12 systems at
+// a stress field (crystal-frame resolved shears), FP64 out, [12][V].
+template <typename T>
+__global__ __launch_bounds__(256) void k_gdot(const T* __restrict__ sig, const T* __restrict__ quat,
+                                              const T* __restrict__ rho, double* __restrict__ out,
+                                              size_t V, Mat m, double gdot0) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double R[9], s[6], sc[6];
+    quat_rot<double>(quat[g], quat[V + g], quat[2 * V + g], quat[3 * V + g], R);
+    for (int k = 0; k < 6; ++k) s[k] = sig[k * V + g];
+    to_crystal(R, s, sc);
+    const double itauc = 1.0 / (m.tau0 + m.taylor * sqrt((double)rho[g]));
+    static_for<0, 12>([&](auto ac) {
+      constexpr int A = decltype(ac)::value;
+      const double x = resolved<A>(sc) * itauc;
+      const double ax = fabs(x);
+      double p;
+      if (m.n_int > 0) {
+        double b = ax;
+        p = 1.0;
+        for (int e = m.n_int; e != 0; e >>= 1) {
+          if (e & 1) p *= b;
+          b *= b;
+        }
+      } else {
+        p = ax > 0.0 ? exp(m.n * log(ax)) : 0.0;
+      }
+      out[(size_t)A * V + g] = x < 0.0 ? -gdot0 * p : gdot0 * p;
+    });
+  }
+}
+
 __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ p, int n, double* out) {
   double v[2] = {0.0, 0.0};
   for (int b = threadIdx.x; b < n; b += 256) {
@@ -1048,6 +1080,13 @@ hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStr
 }
 
 template <typename T>
+hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, size_t V, const Mat& m,
+                       double gdot0, hipStream_t s) {
+  hipLaunchKernelGGL(k_gdot<T>, dim3(grid_for(V)), dim3(256), 0, s, sig, quat, rho, out, V, m, gdot0);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
                          int nblocks, double* out2, hipStream_t s) {
   hipLaunchKernelGGL(k_ingest<T>, dim3(nblocks), dim3(256), 0, s, q, rho, qo, ro, V, partial);
@@ -1085,6 +1124,8 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_ypass<T, true>(int, int, const YArgs<T>&, hipStream_t);           \
   template hipError_t launch_zgamma<T>(int, const ZArgs<T>&, hipStream_t);                     \
   template hipError_t launch_state<T>(const StateArgs<T>&, int, double*, hipStream_t);         \
+  template hipError_t launch_gdot<T>(const T*, const T*, const T*, double*, size_t, const Mat&, double, \
+                                     hipStream_t);                                            \
   template hipError_t launch_ingest<T>(const double*, const double*, T*, T*, size_t, double*, int, \
                                        double*, hipStream_t);                                  \
   template hipError_t launch_export<T>(const T*, double*, size_t, int, int, hipStream_t);      \

@@ -35,6 +35,9 @@ def test_error_paths(require_gpu):
     with pytest.raises(FftevpError) as e:
         s.step()
     assert e.value.status == ESTATE
+    with pytest.raises(FftevpError) as e:
+        s.field("gdot")
+    assert e.value.status == ESTATE
     quat, rho = micro((16, 16, 16), 4, 3)
     bad = quat.copy()
     bad[:, 5] *= 1.01
@@ -116,7 +119,7 @@ def test_non_integral_exponent_matches_oracle(require_gpu):
         ro = o.increment(Loading(), tol=1e-11, max_iter=3000)
         assert r.status == 0
         assert abs(r.Sigma[2] - ro["Sigma"][2]) < 1e-10 * abs(ro["Sigma"][2])
-    for k in ("sigma", "strain", "epsp", "rho"):
+    for k in ("sigma", "strain", "epsp", "rho", "gdot"):
         g = s.field(k).cpu().numpy()
         v = o.field(k)
         assert np.abs(g - v).max() < 1e-10 * np.abs(v).max(), k

@@ -42,7 +42,7 @@ def micro(shape, n_grains, seed, lognormal=True):
 
 
 def oracle_fields(o):
-    return {k: o.field(k) for k in ("sigma", "strain", "epsp", "rho")}
+    return {k: o.field(k) for k in ("sigma", "strain", "epsp", "rho", "gdot")}
 
 
 def test_first_iterate_matches_local_solve(require_gpu):

@@ -110,6 +110,29 @@ def test_schmid_factors_for_001_loading():
     assert np.allclose(np.sort(np.abs(tau)), [0] * 4 + [1 / np.sqrt(6)] * 8, atol=1e-15)
 
 
+def test_gdot_field_uniaxial_single_crystal():
+    """Slip-rate field under uniaxial [001] stress on an unrotated crystal:
+    system a carries gdot0 |s f_a / tauc|^n sign(s f_a) with the Schmid factor
+    f_a = (n_a . e3)(d_a . e3) taken from the plane normals and directions
+    (eight systems at |f| = 1/sqrt6, four at 0), in the order of the system
+    list, and the rates sum to a compressive plastic rate along e3."""
+    shape = (8, 8, 8)
+    quat, rho = uniform(shape, IDQ)
+    o = Oracle(shape, quat, rho)
+    s = -80.0
+    o.sigma = np.tile(voigt_to_mandel(np.array([0, 0, s, 0, 0, 0.0])), (o.nvox, 1))
+    g = o.field("gdot")
+    assert g.shape == (12, o.nvox)
+    n, d = slip_systems()
+    f = n[:, 2] * d[:, 2]
+    tauc = 5.0 + 0.5 * 47337.0 * 2.56e-10 * 1e6
+    want = 1e-3 * np.abs(s * f / tauc) ** 10 * np.sign(s * f)
+    assert np.allclose(np.sort(np.abs(f)), [0] * 4 + [1 / np.sqrt(6)] * 8, atol=1e-15)
+    assert np.allclose(g, want[:, None], rtol=1e-13, atol=0)
+    # plastic rate along e3: sum_a gdot_a f_a < 0 under compression
+    assert (want * f).sum() < 0
+
+
 def test_plastic_rate_is_traceless():
     st = synth.random_voxel_states(64, seed=3)
     _, _, m = voxel_material(st["quat"], C11, C12, C44)
