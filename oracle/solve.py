@@ -37,6 +37,7 @@ import numpy as np
 
 from . import local as L
 from .crystal import voxel_material
+from .gnd import gnd_rates, next_leff
 from .green import gamma_field, green_apply
 from .tensors import (isotropic_c4, mandel_to_voigt, voigt_to_mandel, c4_to_mandel)
 
@@ -91,7 +92,9 @@ class Oracle:
         self.flow = flow or Flow()
         self.plastic = plastic
         self.elastic = (C11, C12, C44)
+        self.quat = np.asarray(quat, dtype=np.float64).reshape(4, -1).copy()
         self.C, self.S, self.m = voxel_material(quat, C11, C12, C44)
+        self.gnd = None
         lam0, mu0 = c0 if c0 is not None else default_c0(C11, C12, C44)
         self.c0 = (lam0, mu0)
         self.C0_4 = isotropic_c4(lam0, mu0)
@@ -104,6 +107,11 @@ class Oracle:
         self.E = np.zeros(6)
         self.t = 0.0
         self._G = None
+
+    def enable_gnd(self, grains, l0, xi):
+        """Track GND densities (Sec. 2.2, Eq. 7-8; see oracle.gnd) from now on."""
+        self.gnd = dict(grains=np.asarray(grains).reshape(-1).copy(), leff=float(l0), xi=float(xi),
+                        rs=np.zeros((12, self.nvox)), ret=np.zeros((12, self.nvox)))
 
     # -- helpers ----------------------------------------------------------
     def tauc(self, rho=None, flow=None):
@@ -176,6 +184,12 @@ class Oracle:
         gsum = np.abs(gdot).sum(axis=1)
         self.rho = self.rho + load.dt * (f.k1 * np.sqrt(self.rho) - f.k2 * self.rho) * gsum
         self.sigma, self.e, self.E = sig, e, E
+        if self.gnd is not None:
+            G = self.gnd
+            rs, ret = gnd_rates(gdot.T, self.quat, G["grains"], self.shape, f.b, G["leff"])
+            G["rs"] = G["rs"] + load.dt * rs
+            G["ret"] = G["ret"] + load.dt * ret
+            G["leff"] = next_leff(G["leff"], E, G["xi"])
         self.t += load.dt
         rep = dict(iters=iters, converged=converged, err_c=err_c, err_bc=err_bc,
                    Sigma=mandel_to_voigt(sig.mean(axis=0)), E=mandel_to_voigt(E),
@@ -191,6 +205,8 @@ class Oracle:
             return mandel_to_voigt(a.T)
         if name == "rho":
             return self.rho.copy()
+        if name in ("rho_gnds", "rho_gndet"):
+            return self.gnd["rs" if name == "rho_gnds" else "ret"].copy()
         if name == "gdot":
             # flow rule (Eq. 2, power law of reading R1) at the committed stress
             # and the current density, [12][V]
