@@ -61,7 +61,9 @@ typedef enum {
   FFTEVP_FIELD_RHO = 3,         /* dislocation density, 1 comp                    */
   FFTEVP_FIELD_SIGMA_ITER = 4,  /* stress of the latest iteration, 6 comps        */
   FFTEVP_FIELD_STRAIN_ITER = 5, /* compatible strain after the latest iteration   */
-  FFTEVP_FIELD_GDOT = 6         /* slip rates of the 12 systems, 1/s (see below)  */
+  FFTEVP_FIELD_GDOT = 6,        /* slip rates of the 12 systems, 1/s (see below)  */
+  FFTEVP_FIELD_RHO_GNDS = 7,    /* screw GND density per system, 12 comps, m^-2   */
+  FFTEVP_FIELD_RHO_GNDET = 8    /* edge GND density per system, 12 comps, m^-2    */
 } fftevp_field;
 
 typedef struct fftevp_ctx fftevp_ctx;
@@ -118,6 +120,7 @@ typedef struct {
   int iters, newton_max_seen, newton_failed;
   double err_c, err_bc, Sigma[6], E[6], rho_mean;
   double newton_mean, linesearch_mean;
+  double l_eff; /* effective length after the increment (m); 0 without GND */
 } fftevp_report;
 
 /* Create a context for an n0 x n1 x n2 grid (x, y, z), each a power of two
@@ -140,6 +143,23 @@ fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat_dev,
                                         const double* rho_dev);
 
 fftevp_status fftevp_set_loading(fftevp_ctx* ctx, const fftevp_loading* loading);
+
+/* Geometrically necessary dislocation densities (Sec. 2.2, Eq. 7-8). From
+ * this call on, every committed increment adds dt times the rates
+ *   screw: -(1/b) grad(gdot_a) . t_a,   edge: (1/b) grad(gdot_a) . d_a
+ * per slip system a (t = n x d, rotated to the sample frame; gdot_a the
+ * increment's converged slip rates, density from the increment's start) to
+ * two per-system density fields that start at zero, then multiplies the
+ * effective length l_eff (the gradient's grid spacing, initially l0) by
+ * (1 + eps_vm / xi), eps_vm the von Mises equivalent of the new mean strain.
+ * The gradient is a finite difference on the periodic grid: central where
+ * both neighbours along an axis belong to the voxel's grain, one-sided
+ * towards the one that does, zero where neither does. grain_dev: device
+ * int32 [V], one grain id per voxel, copied. l0, xi: finite, > 0 (EINVAL).
+ * Calling it again restarts the densities and l_eff. Snapshots taken while
+ * GND is tracked hold the densities and l_eff and load only into a context
+ * that tracks GND too. The densities do not act back on the solve. */
+fftevp_status fftevp_set_gnd(fftevp_ctx* ctx, const int* grain_dev, double l0, double xi);
 
 /* One strain increment: the fixed-point solve, then the explicit update of
  * plastic strain and density at the converged stress (Eq. 1 first-order
@@ -185,12 +205,12 @@ fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
  * kernel class k with HIP events on the context's stream: 0 local solve +
  * x-FFTs, 1 (unused), 2 forward y-FFT + first reduction stage, 3 z-FFT +
  * Green operator + stop test, 4 inverse y-FFT, 5 end-of-increment update,
- * 6 adjoint set-up and reverse update. Durations of launches that did work
- * (not those skipped after convergence) are summed per class.
+ * 6 adjoint set-up and reverse update, 7 GND update. Durations of launches
+ * that did work (not those skipped after convergence) are summed per class.
  * fftevp_get_profile copies the sums (ms) and launch counts into caller
  * arrays of FFTEVP_NPROF entries and, if reset != 0, clears them. Each timed
  * launch adds about 4 us of event overhead to the stream. */
-#define FFTEVP_NPROF 7
+#define FFTEVP_NPROF 8
 fftevp_status fftevp_set_profiling(fftevp_ctx* ctx, int class_mask);
 fftevp_status fftevp_get_profile(fftevp_ctx* ctx, double* ms, long long* launches, int reset);
 

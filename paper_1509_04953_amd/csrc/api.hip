@@ -31,6 +31,11 @@ struct Bufs {
   void* a_eta = nullptr;   // eigenstrain of the adjoint solve, [6][V]
   void* a_sigt = nullptr;  // forward stress of the increment, [6][V]
   void* a_rho = nullptr;   // density at the start of the increment, [V]
+  // GND densities (allocated by set_gnd)
+  int* grain = nullptr;    // grain ids, [V]
+  void* gd = nullptr;      // slip rates of the increment (scratch), [12][V]
+  void* gnds = nullptr;    // screw GND density per system, [12][V]
+  void* gndet = nullptr;   // edge GND density per system, [12][V]
 };
 
 }  // namespace
@@ -58,6 +63,8 @@ struct fftevp_ctx {
   double* red2 = nullptr;
   double* red2_h = nullptr;  // pinned
   double E[6] = {0, 0, 0, 0, 0, 0};  // committed macroscopic strain (Mandel)
+  bool gnd_on = false;
+  double leff = 0.0, xi = 0.0;  // effective length (m) and its constant
   double t = 0.0;
   double inc = 0.0;
   int last_iters = 0;
@@ -279,6 +286,10 @@ void free_all(fftevp_ctx* ctx) {
   for (auto p : ctx->b.emain) f(p);
   for (auto p : ctx->b.enyq) f(p);
   f(ctx->b.tmain);
+  f(ctx->b.grain);
+  f(ctx->b.gd);
+  f(ctx->b.gnds);
+  f(ctx->b.gndet);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->b.a_eta);
   f(ctx->b.a_sigt);
@@ -465,6 +476,34 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     ctx->e_last = ctx->ec;
     std::swap(ctx->sc, ctx->sw);
     for (int q = 0; q < 6; ++q) ctx->E[q] = so.ctl.E[q];
+    if (ctx->gnd_on) {
+      // slip rates at the converged stress with the increment's start density,
+      // then the GND update with the current effective length (Eq. 7)
+      GndArgs<T> ga{};
+      ga.quat = (const T*)ctx->b.quat;
+      ga.grain = ctx->b.grain;
+      ga.gd = (T*)ctx->b.gd;
+      ga.rs = (T*)ctx->b.gnds;
+      ga.ret = (T*)ctx->b.gndet;
+      ga.V = ctx->V;
+      ga.n0 = ctx->n0;
+      ga.n1 = ctx->n1;
+      ga.n2 = ctx->n2;
+      ga.dt = dt;
+      ga.inv_b = 1.0 / ctx->flow.b;
+      ga.inv_h = 1.0 / ctx->leff;
+      HIPCHK(timed(ctx, 7, -1, [&] {
+        return launch_gnd<T>(ga, (const T*)ctx->b.sig[ctx->sc], (const T*)ctx->b.rho, m, ctx->flow.gdot0,
+                             ctx->stream);
+      }));
+      // Eq. 8 with the von Mises equivalent of the new mean strain
+      double tr = (ctx->E[0] + ctx->E[1] + ctx->E[2]) / 3.0, ee = 0.0;
+      for (int q = 0; q < 6; ++q) {
+        const double dv = ctx->E[q] - (q < 3 ? tr : 0.0);
+        ee += dv * dv;
+      }
+      ctx->leff *= 1.0 + std::sqrt(2.0 / 3.0 * ee) / ctx->xi;
+    }
     StateArgs<T> sa{};
     sa.sig = (const T*)ctx->b.sig[ctx->sc];
     sa.quat = (const T*)ctx->b.quat;
@@ -500,11 +539,12 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     rep->rho_mean = rho_mean;
     rep->newton_mean = so.ctl.nsum / (double)ctx->V;
     rep->linesearch_mean = so.ctl.lssum / (double)ctx->V;
+    rep->l_eff = ctx->gnd_on ? ctx->leff : 0.0;
   }
   return ret;
 }
 
-size_t snap_layout(const fftevp_ctx* c, size_t off[6]) {
+size_t snap_layout(const fftevp_ctx* c, size_t off[8]) {
   const size_t ts = c->tsize, V = c->V;
   size_t o = kHeader * sizeof(double);
   off[0] = o;  // epsp
@@ -518,7 +558,10 @@ size_t snap_layout(const fftevp_ctx* c, size_t off[6]) {
   off[4] = o;  // strain Nyquist planes
   o += 6 * c->planes * ts;
   o = (o + 255) & ~(size_t)255;
-  off[5] = o;
+  off[5] = o;  // GND densities (when tracked): screw then edge, [12][V] each
+  if (c->gnd_on) o += 24 * V * ts;
+  off[6] = o;
+  off[7] = o;
   return o;
 }
 
@@ -547,7 +590,7 @@ fftevp_status adjoint_impl(fftevp_ctx* ctx, const fftevp_opts& o, const void* be
   if (st != FFTEVP_OK) return st;
   if ((st = check_snapshot(ctx, after)) != FFTEVP_OK) return st;
   const size_t V = ctx->V, ts = sizeof(T);
-  size_t off[6];
+  size_t off[8];
   snap_layout(ctx, off);
   if (!ctx->b.a_eta) HIPCHK(hipMalloc(&ctx->b.a_eta, 6 * V * ts));
   AdjArgs<T> aa{};
@@ -727,6 +770,30 @@ fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat, con
   return FFTEVP_OK;
 }
 
+fftevp_status fftevp_set_gnd(fftevp_ctx* ctx, const int* grain_dev, double l0, double xi) {
+  if (!ctx || !grain_dev) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (!(l0 > 0.0 && std::isfinite(l0) && xi > 0.0 && std::isfinite(xi)))
+    return fail(ctx, FFTEVP_EINVAL, "l0 and xi must be finite and positive");
+  const size_t V = ctx->V, ts = ctx->tsize;
+  hipError_t e = hipSuccess;
+  if (!ctx->b.grain) e = hipMalloc((void**)&ctx->b.grain, V * sizeof(int));
+  if (e == hipSuccess && !ctx->b.gd) e = hipMalloc(&ctx->b.gd, 12 * V * ts);
+  if (e == hipSuccess && !ctx->b.gnds) e = hipMalloc(&ctx->b.gnds, 12 * V * ts);
+  if (e == hipSuccess && !ctx->b.gndet) e = hipMalloc(&ctx->b.gndet, 12 * V * ts);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
+  }
+  HIPCHK(hipMemcpyAsync(ctx->b.grain, grain_dev, V * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->b.gnds, 0, 12 * V * ts, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->b.gndet, 0, 12 * V * ts, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->gnd_on = true;
+  ctx->leff = l0;
+  ctx->xi = xi;
+  return FFTEVP_OK;
+}
+
 fftevp_status fftevp_set_loading(fftevp_ctx* ctx, const fftevp_loading* l) {
   if (!ctx || !l) return fail(ctx, FFTEVP_EINVAL, "null argument");
   int nsc = 0;
@@ -795,6 +862,11 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
     case FFTEVP_FIELD_RHO: e = exp(ctx->b.rho, 1, 0); break;
     case FFTEVP_FIELD_SIGMA_ITER: e = exp(ctx->b.sig[ctx->sw], 6, 1); break;
     case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->e_last); break;
+    case FFTEVP_FIELD_RHO_GNDS:
+    case FFTEVP_FIELD_RHO_GNDET:
+      if (!ctx->gnd_on) return fail(ctx, FFTEVP_ESTATE, "GND densities are not tracked (fftevp_set_gnd)");
+      e = exp(field == FFTEVP_FIELD_RHO_GNDS ? ctx->b.gnds : ctx->b.gndet, 12, 0);
+      break;
     case FFTEVP_FIELD_GDOT: {
       if (!ctx->have_mat || !ctx->have_micro)
         return fail(ctx, FFTEVP_ESTATE, "set_material and set_microstructure must come first");
@@ -821,13 +893,13 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
 
 size_t fftevp_state_bytes(const fftevp_ctx* ctx) {
   if (!ctx) return 0;
-  size_t off[6];
+  size_t off[8];
   return snap_layout(ctx, off);
 }
 
 fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   if (!ctx || !dst) return fail(ctx, FFTEVP_EINVAL, "null argument");
-  size_t off[6];
+  size_t off[8];
   snap_layout(ctx, off);
   const size_t ts = ctx->tsize, V = ctx->V;
   double hdr[kHeader] = {0};
@@ -840,6 +912,8 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   hdr[11] = ctx->t;
   hdr[12] = ctx->inc;
   hdr[13] = ctx->last_iters;
+  hdr[14] = ctx->gnd_on ? 1.0 : 0.0;
+  hdr[15] = ctx->leff;
   char* d = (char*)dst;
   HIPCHK(hipMemcpyAsync(d, hdr, sizeof hdr, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(d + off[0], ctx->b.epsp, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -848,13 +922,18 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   HIPCHK(hipMemcpyAsync(d + off[3], ctx->b.emain[ctx->ec], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(d + off[4], ctx->b.enyq[ctx->ec], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
                         ctx->stream));
+  if (ctx->gnd_on) {
+    HIPCHK(hipMemcpyAsync(d + off[5], ctx->b.gnds, 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d + off[5] + 12 * V * ts, ctx->b.gndet, 12 * V * ts, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FFTEVP_OK;
 }
 
 fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   if (!ctx || !src) return fail(ctx, FFTEVP_EINVAL, "null argument");
-  size_t off[6];
+  size_t off[8];
   snap_layout(ctx, off);
   const size_t ts = ctx->tsize, V = ctx->V;
   double hdr[kHeader];
@@ -862,7 +941,7 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   HIPCHK(hipMemcpyAsync(hdr, s, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
-      hdr[4] != ctx->n2)
+      hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0))
     return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
   HIPCHK(hipMemcpyAsync(ctx->b.epsp, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.rho, s + off[1], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -870,6 +949,12 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   HIPCHK(hipMemcpyAsync(ctx->b.emain[ctx->ec], s + off[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.enyq[ctx->ec], s + off[4], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
                         ctx->stream));
+  if (ctx->gnd_on) {
+    HIPCHK(hipMemcpyAsync(ctx->b.gnds, s + off[5], 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->b.gndet, s + off[5] + 12 * V * ts, 12 * V * ts, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    ctx->leff = hdr[15];
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < 6; ++k) ctx->E[k] = hdr[5 + k];
   ctx->t = hdr[11];

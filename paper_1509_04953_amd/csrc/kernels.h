@@ -99,6 +99,19 @@ struct ZArgs {
   double c0l, c0m, ci_d, ci_o, ci_s;
 };
 
+// GND update (Sec. 2.2, Eq. 7-8)
+template <typename T>
+struct GndArgs {
+  const T* quat;      // [4][V]
+  const int* grain;   // [V] grain ids
+  T* gd;              // scratch: slip rates of the increment, [12][V]
+  T* rs;              // screw GND density per system (in/out), [12][V]
+  T* ret;             // edge GND density per system (in/out), [12][V]
+  size_t V;
+  int n0, n1, n2;
+  double dt, inv_b, inv_h;  // increment, 1/b (1/m), 1/l_eff (1/m)
+};
+
 template <typename T>
 struct StateArgs {
   const T* sig;
@@ -150,6 +163,9 @@ hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStr
 template <typename T>
 hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, size_t V, const Mat& m,
                        double gdot0, hipStream_t s);
+template <typename T>
+hipError_t launch_gnd(const GndArgs<T>& a, const T* sig, const T* rho, const Mat& m, double gdot0,
+                      hipStream_t s);
 template <typename T>
 hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
                          int nblocks, double* out2, hipStream_t s);

@@ -745,9 +745,9 @@ __global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
 
 // Slip rates gdot_a = gdot0 |tau_a / tauc|^n sign(tau_a) of the 12 systems at
 // a stress field (crystal-frame resolved shears), FP64 out, [12][V].
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_gdot(const T* __restrict__ sig, const T* __restrict__ quat,
-                                              const T* __restrict__ rho, double* __restrict__ out,
+                                              const T* __restrict__ rho, TO* __restrict__ out,
                                               size_t V, Mat m, double gdot0) {
   for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
     double R[9], s[6], sc[6];
@@ -770,8 +770,88 @@ __global__ __launch_bounds__(256) void k_gdot(const T* __restrict__ sig, const T
       } else {
         p = ax > 0.0 ? exp(m.n * log(ax)) : 0.0;
       }
-      out[(size_t)A * V + g] = x < 0.0 ? -gdot0 * p : gdot0 * p;
+      out[(size_t)A * V + g] = (TO)(x < 0.0 ? -gdot0 * p : gdot0 * p);
     });
+  }
+}
+
+// Crystal-frame slip plane normals and directions of the 12 systems (the
+// same list as the Schmid sign table: unnormalised integer vectors, |n| =
+// sqrt3, |d| = sqrt2), and the check that sym(d x n) reproduces the table.
+constexpr int kN[12][3] = {{1, 1, 1},  {1, 1, 1},  {1, 1, 1},  {-1, 1, 1}, {-1, 1, 1}, {-1, 1, 1},
+                           {1, -1, 1}, {1, -1, 1}, {1, -1, 1}, {1, 1, -1}, {1, 1, -1}, {1, 1, -1}};
+constexpr int kD[12][3] = {{0, 1, -1}, {1, 0, -1}, {1, -1, 0}, {0, 1, -1}, {1, 0, 1}, {1, 1, 0},
+                           {0, 1, 1},  {1, 0, -1}, {1, 1, 0},  {0, 1, 1},  {1, 0, 1}, {1, -1, 0}};
+__host__ __device__ constexpr bool nd_match_sign_table() {
+  const int pi[3] = {1, 0, 0}, pj[3] = {2, 2, 1};  // Mandel shear slots 23, 13, 12
+  for (int a = 0; a < 12; ++a) {
+    for (int i = 0; i < 3; ++i)
+      if (kD[a][i] * kN[a][i] != kSign[a][i]) return false;
+    for (int k = 0; k < 3; ++k)
+      if (kD[a][pi[k]] * kN[a][pj[k]] + kD[a][pj[k]] * kN[a][pi[k]] != kSign[a][3 + k]) return false;
+    if (kN[a][0] * kD[a][0] + kN[a][1] * kD[a][1] + kN[a][2] * kD[a][2] != 0) return false;
+  }
+  return true;
+}
+static_assert(nd_match_sign_table(), "slip normals/directions disagree with the Schmid sign table");
+
+// GND densities (Sec. 2.2, Eq. 7-8): per system, rates -(1/b) grad(gdot).t
+// (screw) and (1/b) grad(gdot).d (edge), t = n x d, rotated to the sample
+// frame; the gradient is a finite difference with spacing l_eff, central
+// where both neighbours along an axis share the voxel's grain, one-sided
+// towards the one that does, zero if neither does; periodic grid. One
+// thread per voxel; workgroups renumbered so each XCD takes a contiguous
+// range of voxels (neighbours along y and z then share its L2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
+  const int nb = gridDim.x;
+  int b = blockIdx.x;
+  if (FFTEVP_XCD_REMAP && nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
+  const size_t g = (size_t)b * 256 + threadIdx.x;
+  if (g >= a.V) return;
+  const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+  const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
+  // neighbour offsets and stencil weights per axis: D = wp f(+) + wc f(0) + wm f(-)
+  const size_t sx = 1, sy = (size_t)n0, sz = (size_t)n0 * n1;
+  const size_t gp[3] = {x + 1 < n0 ? g + sx : g + sx - (size_t)n0 * sx,
+                        y + 1 < n1 ? g + sy : g + sy - (size_t)n1 * sy,
+                        z + 1 < n2 ? g + sz : g + sz - (size_t)n2 * sz};
+  const size_t gm[3] = {x > 0 ? g - sx : g - sx + (size_t)n0 * sx, y > 0 ? g - sy : g - sy + (size_t)n1 * sy,
+                        z > 0 ? g - sz : g - sz + (size_t)n2 * sz};
+  const int me = a.grain[g];
+  double wp[3], wc[3], wm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const bool p = a.grain[gp[k]] == me, m = a.grain[gm[k]] == me;
+    wp[k] = p ? (m ? 0.5 : 1.0) : 0.0;
+    wm[k] = m ? (p ? -0.5 : -1.0) : 0.0;
+    wc[k] = (p && !m) ? -1.0 : ((m && !p) ? 1.0 : 0.0);
+  }
+  double R[9];
+  quat_rot<double>(a.quat[g], a.quat[a.V + g], a.quat[2 * a.V + g], a.quat[3 * a.V + g], R);
+  const double s_n = 0.57735026918962576451, s_d = kIR2;
+  const double cs = a.dt * a.inv_b * a.inv_h;
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const T* f = a.gd + (size_t)al * a.V;
+    const double f0 = f[g];
+    double D[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) D[k] = wp[k] * (double)f[gp[k]] + wc[k] * f0 + wm[k] * (double)f[gm[k]];
+    // crystal-frame d and t = n x d (unit), rotated: R v
+    const double dc[3] = {s_d * kD[al][0], s_d * kD[al][1], s_d * kD[al][2]};
+    const double nc[3] = {s_n * kN[al][0], s_n * kN[al][1], s_n * kN[al][2]};
+    const double tc[3] = {nc[1] * dc[2] - nc[2] * dc[1], nc[2] * dc[0] - nc[0] * dc[2], nc[0] * dc[1] - nc[1] * dc[0]};
+    double gd_ = 0.0, gt = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double di = R[3 * i] * dc[0] + R[3 * i + 1] * dc[1] + R[3 * i + 2] * dc[2];
+      const double ti = R[3 * i] * tc[0] + R[3 * i + 1] * tc[1] + R[3 * i + 2] * tc[2];
+      gd_ += D[i] * di;
+      gt += D[i] * ti;
+    }
+    a.rs[(size_t)al * a.V + g] = (T)((double)a.rs[(size_t)al * a.V + g] - cs * gt);
+    a.ret[(size_t)al * a.V + g] = (T)((double)a.ret[(size_t)al * a.V + g] + cs * gd_);
   }
 }
 
@@ -1082,7 +1162,19 @@ hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStr
 template <typename T>
 hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, size_t V, const Mat& m,
                        double gdot0, hipStream_t s) {
-  hipLaunchKernelGGL(k_gdot<T>, dim3(grid_for(V)), dim3(256), 0, s, sig, quat, rho, out, V, m, gdot0);
+  hipLaunchKernelGGL((k_gdot<T, double>), dim3(grid_for(V)), dim3(256), 0, s, sig, quat, rho, out, V, m, gdot0);
+  return hipGetLastError();
+}
+
+// GND update of one increment: slip rates at the converged stress (density
+// from the increment's start) into gd, then the grain-aware gradient update.
+template <typename T>
+hipError_t launch_gnd(const GndArgs<T>& a, const T* sig, const T* rho, const Mat& m, double gdot0,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_gdot<T, T>), dim3(grid_for(a.V)), dim3(256), 0, s, sig, a.quat, rho, a.gd, a.V, m,
+                     gdot0);
+  const int nb = (int)((a.V + 255) / 256);
+  hipLaunchKernelGGL(k_gnd<T>, dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1126,6 +1218,7 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_state<T>(const StateArgs<T>&, int, double*, hipStream_t);         \
   template hipError_t launch_gdot<T>(const T*, const T*, const T*, double*, size_t, const Mat&, double, \
                                      hipStream_t);                                            \
+  template hipError_t launch_gnd<T>(const GndArgs<T>&, const T*, const T*, const Mat&, double, hipStream_t); \
   template hipError_t launch_ingest<T>(const double*, const double*, T*, T*, size_t, double*, int, \
                                        double*, hipStream_t);                                  \
   template hipError_t launch_export<T>(const T*, double*, size_t, int, int, hipStream_t);      \

@@ -18,10 +18,12 @@ _lib = None
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENONFINITE, ELOCAL, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
-FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5, "gdot": 6}
-NPROF = 7
-PROF_NAMES = ("local", "unused", "yfwd", "zgamma", "yinv", "state", "adjoint")
-NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6, "gdot": 12}
+FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5, "gdot": 6,
+          "rho_gnds": 7, "rho_gndet": 8}
+NPROF = 8
+PROF_NAMES = ("local", "unused", "yfwd", "zgamma", "yinv", "state", "adjoint", "gnd")
+NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6, "gdot": 12,
+         "rho_gnds": 12, "rho_gndet": 12}
 
 
 class Cubic(C.Structure):
@@ -46,7 +48,7 @@ class ReportC(C.Structure):
     _fields_ = [("iters", C.c_int), ("newton_max_seen", C.c_int), ("newton_failed", C.c_int),
                 ("err_c", C.c_double), ("err_bc", C.c_double), ("Sigma", C.c_double * 6),
                 ("E", C.c_double * 6), ("rho_mean", C.c_double),
-                ("newton_mean", C.c_double), ("linesearch_mean", C.c_double)]
+                ("newton_mean", C.c_double), ("linesearch_mean", C.c_double), ("l_eff", C.c_double)]
 
 
 def library():
@@ -64,6 +66,7 @@ def library():
         "fftevp_set_material": (I, [P, C.POINTER(Cubic), C.POINTER(FlowC)]),
         "fftevp_set_microstructure": (I, [P, P, P]),
         "fftevp_set_loading": (I, [P, C.POINTER(LoadingC)]),
+        "fftevp_set_gnd": (I, [P, P, C.c_double, C.c_double]),
         "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_get_field": (I, [P, I, P]),
         "fftevp_state_bytes": (S, [P]),
@@ -138,6 +141,7 @@ class Report:
     rho_mean: float
     newton_mean: float = 0.0
     linesearch_mean: float = 0.0
+    l_eff: float = 0.0
 
 
 def _opts(o: Opts | None):
@@ -197,6 +201,17 @@ class Solver:
         self._check(self.lib.fftevp_set_microstructure(self.h, C.c_void_p(q.data_ptr()),
                                                        C.c_void_p(r.data_ptr())))
 
+    def set_gnd(self, grains, l0: float = 21.4e-6, xi: float = 200.0):
+        """Track GND densities (screw and edge, per slip system) from every
+        committed increment on; ``grains`` holds one integer grain id per
+        voxel, ``l0`` the grid spacing (m), ``xi`` the effective-length
+        constant."""
+        g = self.torch.as_tensor(np.asarray(grains).reshape(-1), dtype=self.torch.int32,
+                                 device="cuda").contiguous()
+        if g.numel() != self.nvox:
+            raise ValueError("one grain id per voxel")
+        self._check(self.lib.fftevp_set_gnd(self.h, C.c_void_p(g.data_ptr()), float(l0), float(xi)))
+
     def set_loading(self, ld: Load):
         c = LoadingC((C.c_double * 6)(*ld.Edot), (C.c_double * 6)(*ld.Sigma),
                      (C.c_int * 6)(*ld.strain_ctrl), ld.dt)
@@ -207,7 +222,7 @@ class Solver:
         st = self._check(self.lib.fftevp_step(self.h, C.byref(_opts(opts)), C.byref(r)), allow)
         return Report(st, r.iters, r.newton_max_seen, r.newton_failed, r.err_c, r.err_bc,
                       np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean, r.newton_mean,
-                      r.linesearch_mean)
+                      r.linesearch_mean, r.l_eff)
 
     def field(self, name: str):
         n = NCOMP[name]
