@@ -122,6 +122,36 @@ def run_adjoint(w, quat, rho, precision, increments=None):
             "grad": th.grad.numpy().tolist()}
 
 
+def run_gnd(w, quat, rho, grains, precision, increments=4):
+    """GND update (grain-aware slip-rate gradients, Sec. 2.2 Eq. 7-8) on the
+    same workload: HIP-event time of the GND kernel per increment and its HBM
+    roofline."""
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load(dt=w.dt))
+    s.set_gnd(grains.reshape(-1))
+    opts = Opts(tol=w.tol, max_iter=2000)
+    s.step(opts)
+    s.set_profiling(True, classes=("gnd",))
+    s.profile(reset=True)
+    for _ in range(increments):
+        r = s.step(opts)
+    ms, n = s.profile(reset=True)["gnd"]
+    s.close()
+    word = 8 if precision == "fp64" else 4
+    V = w.voxels
+    # the GND kernel: slip rates 12, orientation 4, densities 24 in (+ int32
+    # grain id), densities 24 out (the state update writes the 12 rates)
+    nbytes = 64 * V * word + 4 * V
+    avg = ms / max(n, 1)
+    gbs = nbytes / (avg * 1e-3) / 1e9
+    return {"precision": precision, "ms_per_increment": avg, "increments": n,
+            "bytes_per_increment": nbytes, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+            "l_eff_m": r.l_eff}
+
+
 def source_hash():
     """Prefix of the sha256 of the device sources (matches the profiles)."""
     import hashlib
@@ -247,6 +277,7 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-gnd", action="store_true")
     ap.add_argument("--adjoint-workload", default="cu128adj")
     ap.add_argument("--adjoint-increments", type=int, default=0,
                     help="increments of the adjoint run (default: the workload's)")
@@ -270,7 +301,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copies": 3}))
         return
     w = synth.workload(args.workload)
-    quat, rho, _ = synth.make_microstructure(w)
+    quat, rho, grains = synth.make_microstructure(w)
     quat = quat.reshape(4, -1)
     rho = rho.reshape(-1)
     out = {}
@@ -311,6 +342,8 @@ def main():
                          "iterations": sum(m["iters"]), "roofline": mroof, "kernels": mk,
                          "s33_rel_diff_vs_fp64": float(np.max(np.abs(np.array(m["s33"]) - np.array(r["s33"])))
                                                        / np.max(np.abs(r["s33"])))}
+    if not args.no_gnd:
+        line["gnd"] = run_gnd(w, quat, rho, grains, precs[0])
     if not args.no_adjoint:
         wa = synth.workload(args.adjoint_workload)
         if wa.name == w.name:

@@ -476,34 +476,6 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     ctx->e_last = ctx->ec;
     std::swap(ctx->sc, ctx->sw);
     for (int q = 0; q < 6; ++q) ctx->E[q] = so.ctl.E[q];
-    if (ctx->gnd_on) {
-      // slip rates at the converged stress with the increment's start density,
-      // then the GND update with the current effective length (Eq. 7)
-      GndArgs<T> ga{};
-      ga.quat = (const T*)ctx->b.quat;
-      ga.grain = ctx->b.grain;
-      ga.gd = (T*)ctx->b.gd;
-      ga.rs = (T*)ctx->b.gnds;
-      ga.ret = (T*)ctx->b.gndet;
-      ga.V = ctx->V;
-      ga.n0 = ctx->n0;
-      ga.n1 = ctx->n1;
-      ga.n2 = ctx->n2;
-      ga.dt = dt;
-      ga.inv_b = 1.0 / ctx->flow.b;
-      ga.inv_h = 1.0 / ctx->leff;
-      HIPCHK(timed(ctx, 7, -1, [&] {
-        return launch_gnd<T>(ga, (const T*)ctx->b.sig[ctx->sc], (const T*)ctx->b.rho, m, ctx->flow.gdot0,
-                             ctx->stream);
-      }));
-      // Eq. 8 with the von Mises equivalent of the new mean strain
-      double tr = (ctx->E[0] + ctx->E[1] + ctx->E[2]) / 3.0, ee = 0.0;
-      for (int q = 0; q < 6; ++q) {
-        const double dv = ctx->E[q] - (q < 3 ? tr : 0.0);
-        ee += dv * dv;
-      }
-      ctx->leff *= 1.0 + std::sqrt(2.0 / 3.0 * ee) / ctx->xi;
-    }
     StateArgs<T> sa{};
     sa.sig = (const T*)ctx->b.sig[ctx->sc];
     sa.quat = (const T*)ctx->b.quat;
@@ -516,7 +488,33 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     sa.k1 = ctx->flow.k1;
     sa.k2 = ctx->flow.k2;
     sa.m = m;
+    sa.gd = ctx->gnd_on ? (T*)ctx->b.gd : nullptr;
     HIPCHK(timed(ctx, 5, -1, [&] { return launch_state<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    if (ctx->gnd_on) {
+      // GND update from the increment's slip rates (k_state evaluated them at
+      // the converged stress with the start density) and the current
+      // effective length (Eq. 7), then Eq. 8 with the new mean strain
+      GndArgs<T> ga{};
+      ga.quat = (const T*)ctx->b.quat;
+      ga.grain = ctx->b.grain;
+      ga.gd = (const T*)ctx->b.gd;
+      ga.rs = (T*)ctx->b.gnds;
+      ga.ret = (T*)ctx->b.gndet;
+      ga.V = ctx->V;
+      ga.n0 = ctx->n0;
+      ga.n1 = ctx->n1;
+      ga.n2 = ctx->n2;
+      ga.dt = dt;
+      ga.inv_b = 1.0 / ctx->flow.b;
+      ga.inv_h = 1.0 / ctx->leff;
+      HIPCHK(timed(ctx, 7, -1, [&] { return launch_gnd<T>(ga, ctx->stream); }));
+      double tr = (ctx->E[0] + ctx->E[1] + ctx->E[2]) / 3.0, ee = 0.0;
+      for (int q = 0; q < 6; ++q) {
+        const double dv = ctx->E[q] - (q < 3 ? tr : 0.0);
+        ee += dv * dv;
+      }
+      ctx->leff *= 1.0 + std::sqrt(2.0 / 3.0 * ee) / ctx->xi;
+    }
     HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->prof) HIPCHK(harvest(ctx, 0, false));

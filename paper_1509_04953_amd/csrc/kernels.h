@@ -104,7 +104,7 @@ template <typename T>
 struct GndArgs {
   const T* quat;      // [4][V]
   const int* grain;   // [V] grain ids
-  T* gd;              // scratch: slip rates of the increment, [12][V]
+  const T* gd;        // slip rates of the increment (written by k_state), [12][V]
   T* rs;              // screw GND density per system (in/out), [12][V]
   T* ret;             // edge GND density per system (in/out), [12][V]
   size_t V;
@@ -119,6 +119,7 @@ struct StateArgs {
   T* epsp;
   T* rho;
   double* partial;  // [blocks][2]: sum rho_new, sum sum_a |gdot_a|
+  T* gd;            // optional out: slip rates of the increment, [12][V] (GND update)
   size_t nvox;
   double dt, gdot0, k1, k2;
   Mat m;
@@ -164,8 +165,7 @@ template <typename T>
 hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, size_t V, const Mat& m,
                        double gdot0, hipStream_t s);
 template <typename T>
-hipError_t launch_gnd(const GndArgs<T>& a, const T* sig, const T* rho, const Mat& m, double gdot0,
-                      hipStream_t s);
+hipError_t launch_gnd(const GndArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
                          int nblocks, double* out2, hipStream_t s);

@@ -737,6 +737,14 @@ __global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
     for (int k = 0; k < 6; ++k) a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
     const double rn = rho + a.dt * (a.k1 * sqrt(rho) - a.k2 * rho) * a.gdot0 * asum;
     a.rho[g] = (T)rn;
+    if (a.gd) {
+      // the increment's slip rates for the GND update: gdot0 |x|^(n-1) x
+      const double itauc = 1.0 / tauc;
+      static_for<0, 12>([&](auto ac) {
+        constexpr int A = decltype(ac)::value;
+        a.gd[(size_t)A * V + g] = (T)(a.gdot0 * w[A] * (resolved<A>(sc) * itauc));
+      });
+    }
     part[0] += (double)(T)rn;
     part[1] += a.gdot0 * asum;
   }
@@ -794,6 +802,21 @@ __host__ __device__ constexpr bool nd_match_sign_table() {
   return true;
 }
 static_assert(nd_match_sign_table(), "slip normals/directions disagree with the Schmid sign table");
+// t = n x d in integers (|t| = sqrt6)
+struct IntVec12 {
+  int v[12][3];
+};
+__host__ __device__ constexpr IntVec12 cross_nd() {
+  IntVec12 r{};
+  for (int a = 0; a < 12; ++a) {
+    r.v[a][0] = kN[a][1] * kD[a][2] - kN[a][2] * kD[a][1];
+    r.v[a][1] = kN[a][2] * kD[a][0] - kN[a][0] * kD[a][2];
+    r.v[a][2] = kN[a][0] * kD[a][1] - kN[a][1] * kD[a][0];
+  }
+  return r;
+}
+constexpr IntVec12 kTv = cross_nd();
+#define kT kTv.v
 
 // GND densities (Sec. 2.2, Eq. 7-8): per system, rates -(1/b) grad(gdot).t
 // (screw) and (1/b) grad(gdot).d (edge), t = n x d, rotated to the sample
@@ -802,6 +825,12 @@ static_assert(nd_match_sign_table(), "slip normals/directions disagree with the 
 // towards the one that does, zero if neither does; periodic grid. One
 // thread per voxel; workgroups renumbered so each XCD takes a contiguous
 // range of voxels (neighbours along y and z then share its L2).
+#ifndef FFTEVP_GND_GROUP
+#define FFTEVP_GND_GROUP 3
+#endif
+constexpr int GND_GROUP = FFTEVP_GND_GROUP;
+static_assert(12 % GND_GROUP == 0, "GND system groups must divide 12");
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
   const int nb = gridDim.x;
@@ -818,6 +847,9 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
                         z + 1 < n2 ? g + sz : g + sz - (size_t)n2 * sz};
   const size_t gm[3] = {x > 0 ? g - sx : g - sx + (size_t)n0 * sx, y > 0 ? g - sy : g - sy + (size_t)n1 * sy,
                         z > 0 ? g - sz : g - sz + (size_t)n2 * sz};
+  const T* __restrict__ gdv = a.gd;
+  T* __restrict__ rsv = a.rs;
+  T* __restrict__ retv = a.ret;
   const int me = a.grain[g];
   double wp[3], wc[3], wm[3];
 #pragma unroll
@@ -829,29 +861,47 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
   }
   double R[9];
   quat_rot<double>(a.quat[g], a.quat[a.V + g], a.quat[2 * a.V + g], a.quat[3 * a.V + g], R);
-  const double s_n = 0.57735026918962576451, s_d = kIR2;
   const double cs = a.dt * a.inv_b * a.inv_h;
+  const double cs_d = cs * kIR2, cs_t = cs * 0.40824829046386301637;  // 1/sqrt2, 1/sqrt6
+  // systems in groups: every load of a group is issued before its arithmetic
+  // and stores, so the latencies overlap
 #pragma unroll
-  for (int al = 0; al < 12; ++al) {
-    const T* f = a.gd + (size_t)al * a.V;
-    const double f0 = f[g];
-    double D[3];
+  for (int grp = 0; grp < 12 / GND_GROUP; ++grp) {
+    T fv[GND_GROUP][7], rv[GND_GROUP], ev[GND_GROUP];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) D[k] = wp[k] * (double)f[gp[k]] + wc[k] * f0 + wm[k] * (double)f[gm[k]];
-    // crystal-frame d and t = n x d (unit), rotated: R v
-    const double dc[3] = {s_d * kD[al][0], s_d * kD[al][1], s_d * kD[al][2]};
-    const double nc[3] = {s_n * kN[al][0], s_n * kN[al][1], s_n * kN[al][2]};
-    const double tc[3] = {nc[1] * dc[2] - nc[2] * dc[1], nc[2] * dc[0] - nc[0] * dc[2], nc[0] * dc[1] - nc[1] * dc[0]};
-    double gd_ = 0.0, gt = 0.0;
+    for (int q = 0; q < GND_GROUP; ++q) {
+      const T* __restrict__ f = gdv + (size_t)(GND_GROUP * grp + q) * a.V;
+      fv[q][0] = f[g];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double di = R[3 * i] * dc[0] + R[3 * i + 1] * dc[1] + R[3 * i + 2] * dc[2];
-      const double ti = R[3 * i] * tc[0] + R[3 * i + 1] * tc[1] + R[3 * i + 2] * tc[2];
-      gd_ += D[i] * di;
-      gt += D[i] * ti;
+      for (int k = 0; k < 3; ++k) {
+        fv[q][1 + k] = f[gp[k]];
+        fv[q][4 + k] = f[gm[k]];
+      }
+      rv[q] = rsv[(size_t)(GND_GROUP * grp + q) * a.V + g];
+      ev[q] = retv[(size_t)(GND_GROUP * grp + q) * a.V + g];
     }
-    a.rs[(size_t)al * a.V + g] = (T)((double)a.rs[(size_t)al * a.V + g] - cs * gt);
-    a.ret[(size_t)al * a.V + g] = (T)((double)a.ret[(size_t)al * a.V + g] + cs * gd_);
+#pragma unroll
+    for (int q = 0; q < GND_GROUP; ++q) {
+      const int al = GND_GROUP * grp + q;
+      double D[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        D[k] = wp[k] * (double)fv[q][1 + k] + wc[k] * (double)fv[q][0] + wm[k] * (double)fv[q][4 + k];
+      // (R v) . D = v . (R^T D) for the integer crystal-frame vectors
+      // d (|d| = sqrt2) and t = n x d (|t| = sqrt6)
+      double u[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] = R[j] * D[0] + R[3 + j] * D[1] + R[6 + j] * D[2];
+      double gd_ = 0.0, gt = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (kD[al][j] > 0) gd_ += u[j];
+        else if (kD[al][j] < 0) gd_ -= u[j];
+        if (kT[al][j] != 0) gt += kT[al][j] * u[j];
+      }
+      rsv[(size_t)al * a.V + g] = (T)((double)rv[q] - cs_t * gt);
+      retv[(size_t)al * a.V + g] = (T)((double)ev[q] + cs_d * gd_);
+    }
   }
 }
 
@@ -1166,13 +1216,9 @@ hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, s
   return hipGetLastError();
 }
 
-// GND update of one increment: slip rates at the converged stress (density
-// from the increment's start) into gd, then the grain-aware gradient update.
+// GND update of one increment from the slip rates k_state left in gd.
 template <typename T>
-hipError_t launch_gnd(const GndArgs<T>& a, const T* sig, const T* rho, const Mat& m, double gdot0,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((k_gdot<T, T>), dim3(grid_for(a.V)), dim3(256), 0, s, sig, a.quat, rho, a.gd, a.V, m,
-                     gdot0);
+hipError_t launch_gnd(const GndArgs<T>& a, hipStream_t s) {
   const int nb = (int)((a.V + 255) / 256);
   hipLaunchKernelGGL(k_gnd<T>, dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
@@ -1218,7 +1264,7 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_state<T>(const StateArgs<T>&, int, double*, hipStream_t);         \
   template hipError_t launch_gdot<T>(const T*, const T*, const T*, double*, size_t, const Mat&, double, \
                                      hipStream_t);                                            \
-  template hipError_t launch_gnd<T>(const GndArgs<T>&, const T*, const T*, const Mat&, double, hipStream_t); \
+  template hipError_t launch_gnd<T>(const GndArgs<T>&, hipStream_t);                          \
   template hipError_t launch_ingest<T>(const double*, const double*, T*, T*, size_t, double*, int, \
                                        double*, hipStream_t);                                  \
   template hipError_t launch_export<T>(const T*, double*, size_t, int, int, hipStream_t);      \
