@@ -37,6 +37,7 @@ import numpy as np
 
 from . import local as L
 from .crystal import voxel_material
+from . import ma_roters as MR
 from .gnd import gnd_rates, next_leff
 from .green import gamma_field, green_apply
 from .tensors import (isotropic_c4, mandel_to_voigt, voigt_to_mandel, c4_to_mandel)
@@ -95,6 +96,7 @@ class Oracle:
         self.quat = np.asarray(quat, dtype=np.float64).reshape(4, -1).copy()
         self.C, self.S, self.m = voxel_material(quat, C11, C12, C44)
         self.gnd = None
+        self.mr = None
         lam0, mu0 = c0 if c0 is not None else default_c0(C11, C12, C44)
         self.c0 = (lam0, mu0)
         self.C0_4 = isotropic_c4(lam0, mu0)
@@ -112,6 +114,19 @@ class Oracle:
         """Track GND densities (Sec. 2.2, Eq. 7-8; see oracle.gnd) from now on."""
         self.gnd = dict(grains=np.asarray(grains).reshape(-1).copy(), leff=float(l0), xi=float(xi),
                         rs=np.zeros((12, self.nvox)), ret=np.zeros((12, self.nvox)))
+
+    def enable_mr(self, law=None):
+        """Use the paper's own flow rule and SSD evolution (Sec. 2.2, Eq. 3-6;
+        see oracle.ma_roters) from now on; each voxel's density is split
+        equally over the 12 systems."""
+        self.mr = law or MR.MaRoters()
+        self.ssd = np.repeat(self.rho[:, None] / 12.0, 12, axis=1)
+
+    def mr_flow(self):
+        G = self.gnd
+        F, P = MR.projections(self.ssd, None if G is None else G["rs"].T,
+                              None if G is None else G["ret"].T)
+        return MR.MRFlow(*MR.slip_parameters(self.mr, F, P)), F, P
 
     # -- helpers ----------------------------------------------------------
     def tauc(self, rho=None, flow=None):
@@ -153,12 +168,19 @@ class Oracle:
         e = self.e + (E - self.E)[None, :]
         lam = self.sigma.copy()
         tauc = self.tauc()
+        if self.mr is not None:
+            mflow, rF, rP = self.mr_flow()
         C0ss_inv = np.linalg.inv(self.C0[np.ix_(s, s)]) if s.any() else None
         hist = []
         converged = False
         for it in range(max_iter):
-            sig, nit, nfail = self.local(lam, e, tauc)
-            eps = self.strain(sig, tauc)
+            if self.mr is None:
+                sig, nit, nfail = self.local(lam, e, tauc)
+                eps = self.strain(sig, tauc)
+            else:
+                sig, nit, nfail = L.local_solve_flow(lam, e, self.epsp, self.S, self.m, self.C0inv,
+                                                     mflow, self._dt)
+                eps = L.constitutive_strain_flow(sig, self.epsp, self.S, self.m, mflow, self._dt)
             err_c = np.sqrt(np.mean(np.sum((e - eps) ** 2, axis=1))) / np.linalg.norm(E)
             Sm = sig.mean(axis=0)
             dS = (Sig_star - Sm)[s]
@@ -179,10 +201,19 @@ class Oracle:
         iters = it + 1
         # state update at the converged stress, density from the increment start
         f = self.flow
-        _, gdot = L.slip_rates(sig, self.m, tauc, self._gdot0(), f.n)
-        self.epsp = self.epsp + load.dt * np.einsum("ma,mak->mk", gdot, self.m)
-        gsum = np.abs(gdot).sum(axis=1)
-        self.rho = self.rho + load.dt * (f.k1 * np.sqrt(self.rho) - f.k2 * self.rho) * gsum
+        if self.mr is None:
+            _, gdot = L.slip_rates(sig, self.m, tauc, self._gdot0(), f.n)
+            self.epsp = self.epsp + load.dt * np.einsum("ma,mak->mk", gdot, self.m)
+            gsum = np.abs(gdot).sum(axis=1)
+            self.rho = self.rho + load.dt * (f.k1 * np.sqrt(self.rho) - f.k2 * self.rho) * gsum
+        else:
+            tau_a = L.resolved_shear(sig, self.m)
+            gdot = mflow.rate(tau_a)
+            epdot = np.einsum("ma,mak->mk", gdot, self.m)
+            self.epsp = self.epsp + load.dt * epdot
+            self.ssd = self.ssd + load.dt * MR.ssd_rates(self.mr, self.ssd, rF, rP, tau_a, gdot,
+                                                         MR.von_mises_stress(sig), MR.von_mises_rate(epdot))
+            self.rho = self.ssd.sum(axis=1)
         self.sigma, self.e, self.E = sig, e, E
         if self.gnd is not None:
             G = self.gnd
@@ -205,11 +236,15 @@ class Oracle:
             return mandel_to_voigt(a.T)
         if name == "rho":
             return self.rho.copy()
+        if name == "rho_ssd":
+            return self.ssd.T.copy()
         if name in ("rho_gnds", "rho_gndet"):
             return self.gnd["rs" if name == "rho_gnds" else "ret"].copy()
         if name == "gdot":
-            # flow rule (Eq. 2, power law of reading R1) at the committed stress
-            # and the current density, [12][V]
+            # flow rule (power law of reading R1, or Eq. 3 with the paper's law)
+            # at the committed stress and the current densities, [12][V]
+            if self.mr is not None:
+                return self.mr_flow()[0].rate(L.resolved_shear(self.sigma, self.m)).T.copy()
             _, g = L.slip_rates(self.sigma, self.m, self.tauc(), self._gdot0(), self.flow.n)
             return g.T.copy()
         raise KeyError(name)
