@@ -63,7 +63,8 @@ typedef enum {
   FFTEVP_FIELD_STRAIN_ITER = 5, /* compatible strain after the latest iteration   */
   FFTEVP_FIELD_GDOT = 6,        /* slip rates of the 12 systems, 1/s (see below)  */
   FFTEVP_FIELD_RHO_GNDS = 7,    /* screw GND density per system, 12 comps, m^-2   */
-  FFTEVP_FIELD_RHO_GNDET = 8    /* edge GND density per system, 12 comps, m^-2    */
+  FFTEVP_FIELD_RHO_GNDET = 8,   /* edge GND density per system, 12 comps, m^-2    */
+  FFTEVP_FIELD_RHO_SSD = 9      /* SSD density per system (paper's law), 12 comps */
 } fftevp_field;
 
 typedef struct fftevp_ctx fftevp_ctx;
@@ -160,6 +161,42 @@ fftevp_status fftevp_set_loading(fftevp_ctx* ctx, const fftevp_loading* loading)
  * GND is tracked hold the densities and l_eff and load only into a context
  * that tracks GND too. The densities do not act back on the solve. */
 fftevp_status fftevp_set_gnd(fftevp_ctx* ctx, const int* grain_dev, double l0, double xi);
+
+/* Constants of the paper's dislocation-based law (Sec. 2.2, Eq. 3-6; Table 1
+ * for Q_slip, Q_bulk, c1..c8). mu and b come from fftevp_flow. */
+typedef struct {
+  double T;               /* temperature, K */
+  double Q_slip, Q_bulk;  /* activation energies, J */
+  double c1, c2, c3;      /* passing stress, jump width, obstacle width */
+  double c4;              /* lock forming, 1/m */
+  double c5;              /* athermal annihilation */
+  double c6;              /* dipole forming, 1/m */
+  double c7;              /* thermal annihilation, m^5 s^(c8-1) */
+  double c8;              /* climb exponent */
+  double nu_D;            /* attempt frequency, 1/s */
+  double poisson;         /* Poisson's ratio */
+} fftevp_mr;
+
+/* Select the flow rule and hardening law. law 0: the power law with the
+ * Kocks-Mecking density above (default). law 1: the paper's law: per slip
+ * system, gdot = gdot_0 exp(-Q_slip/kB T) sinh((|tau| - tau_pass)/tau_cut)
+ * sign(tau) above the passing stress (Eq. 3), with tau_pass = c1 mu b
+ * sqrt(rho_P), tau_cut = Q_slip/(c2 c3 b^2) sqrt(rho_F), gdot_0 = 2 kB T
+ * nu_D sqrt(rho_P)/(c1 c3 mu b^2); forest/parallel densities from the
+ * per-system SSD densities and, when tracked, the GND densities (Eq. 4-5);
+ * SSD evolution (Eq. 6) with the mobile density 2 kB T sqrt(rho_P rho_F)/
+ * (c1 c2 c3 mu b^3), the dipole distance sqrt3 mu b/(16 pi (1-nu) |tau|),
+ * the voxel's von Mises stress and equivalent plastic rate. The parameters
+ * are frozen over an increment (densities of its start) and the densities
+ * advance explicitly from the converged slip rates. law 1 needs
+ * set_material and set_microstructure first (ESTATE) and splits each
+ * voxel's density equally over the 12 systems; set_microstructure repeats
+ * that split. p: constants (EINVAL if missing or out of range; ignored for
+ * law 0). The voxel density field (FFTEVP_FIELD_RHO, report rho_mean) is
+ * then the sum of the 12 SSD densities. The adjoint covers law 0 only
+ * (EINVAL otherwise); snapshots record the law and load only into a
+ * context with the same law. */
+fftevp_status fftevp_set_law(fftevp_ctx* ctx, int law, const fftevp_mr* p);
 
 /* One strain increment: the fixed-point solve, then the explicit update of
  * plastic strain and density at the converged stress (Eq. 1 first-order

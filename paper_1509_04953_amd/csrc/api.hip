@@ -36,6 +36,9 @@ struct Bufs {
   void* gd = nullptr;      // slip rates of the increment (scratch), [12][V]
   void* gnds = nullptr;    // screw GND density per system, [12][V]
   void* gndet = nullptr;   // edge GND density per system, [12][V]
+  // the paper's law (allocated by set_law)
+  void* ssd = nullptr;     // SSD density per system, [12][V]
+  void* sysp = nullptr;    // tau_pass, tau_cut, A per system, [3][12][V]
 };
 
 }  // namespace
@@ -64,6 +67,9 @@ struct fftevp_ctx {
   double* red2_h = nullptr;  // pinned
   double E[6] = {0, 0, 0, 0, 0, 0};  // committed macroscopic strain (Mandel)
   bool gnd_on = false;
+  int law = 0;          // 0: power law (hardening above), 1: the paper's law
+  fftevp_mr mr{};
+  MrConst mrc{};
   double leff = 0.0, xi = 0.0;  // effective length (m) and its constant
   double t = 0.0;
   double inc = 0.0;
@@ -195,6 +201,7 @@ Mat make_mat(const fftevp_ctx* ctx, C0 c0, double dt, double ntol, int newton_ma
   m.tau0 = ctx->flow.tau0;
   m.taylor = ctx->flow.alpha * ctx->flow.mu * ctx->flow.b;
   m.inv_n0 = 1.0 / ctx->n0;
+  m.dt = dt;
   return m;
 }
 
@@ -290,6 +297,8 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.gd);
   f(ctx->b.gnds);
   f(ctx->b.gndet);
+  f(ctx->b.ssd);
+  f(ctx->b.sysp);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->b.a_eta);
   f(ctx->b.a_sigt);
@@ -306,6 +315,18 @@ void free_all(fftevp_ctx* ctx) {
 // ---------------------------------------------------------------------------
 // one fixed-point iteration (forward or tangent) enqueued on the stream
 // ---------------------------------------------------------------------------
+// paper's law: per-system parameters from the current SSD (and GND) densities
+hipError_t mr_params(fftevp_ctx* ctx) {
+  const bool g = ctx->gnd_on;
+  if (ctx->prec == FFTEVP_FP64)
+    return launch_mr_params<double>((const double*)ctx->b.ssd, g ? (const double*)ctx->b.gnds : nullptr,
+                                    g ? (const double*)ctx->b.gndet : nullptr, (double*)ctx->b.sysp, ctx->V,
+                                    ctx->mrc, ctx->stream);
+  return launch_mr_params<float>((const float*)ctx->b.ssd, g ? (const float*)ctx->b.gnds : nullptr,
+                                 g ? (const float*)ctx->b.gndet : nullptr, (float*)ctx->b.sysp, ctx->V, ctx->mrc,
+                                 ctx->stream);
+}
+
 template <typename T, int MODE>
 hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, const void* lam,
                              void* sig_out, const void* epsp, const void* rho, const void* sig_t,
@@ -322,6 +343,7 @@ hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, co
   la.rho = (const T*)rho;
   la.quat = (const T*)ctx->b.quat;
   la.sig_t = (const T*)sig_t;
+  la.sysp = (MODE == MODE_NEWTON && ctx->law == 1) ? (const T*)ctx->b.sysp : nullptr;
   la.partial = ctx->partial;
   la.ctl = ctx->ctl;
   la.tw = (const C*)ctx->b.tw[0];
@@ -489,7 +511,16 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     sa.k2 = ctx->flow.k2;
     sa.m = m;
     sa.gd = ctx->gnd_on ? (T*)ctx->b.gd : nullptr;
-    HIPCHK(timed(ctx, 5, -1, [&] { return launch_state<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    if (ctx->law == 1) {
+      sa.ssd = (T*)ctx->b.ssd;
+      sa.sysp = (const T*)ctx->b.sysp;
+      sa.gnds = ctx->gnd_on ? (const T*)ctx->b.gnds : nullptr;
+      sa.gndet = ctx->gnd_on ? (const T*)ctx->b.gndet : nullptr;
+      sa.mr = ctx->mrc;
+      HIPCHK(timed(ctx, 5, -1, [&] { return launch_state_mr<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    } else {
+      HIPCHK(timed(ctx, 5, -1, [&] { return launch_state<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    }
     if (ctx->gnd_on) {
       // GND update from the increment's slip rates (k_state evaluated them at
       // the converged stress with the start density) and the current
@@ -515,6 +546,8 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
       }
       ctx->leff *= 1.0 + std::sqrt(2.0 / 3.0 * ee) / ctx->xi;
     }
+    // the next increment's frozen parameters of the paper's law
+    if (ctx->law == 1) HIPCHK(mr_params(ctx));
     HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->prof) HIPCHK(harvest(ctx, 0, false));
@@ -558,7 +591,8 @@ size_t snap_layout(const fftevp_ctx* c, size_t off[8]) {
   o = (o + 255) & ~(size_t)255;
   off[5] = o;  // GND densities (when tracked): screw then edge, [12][V] each
   if (c->gnd_on) o += 24 * V * ts;
-  off[6] = o;
+  off[6] = o;  // SSD densities per system (paper's law), [12][V]
+  if (c->law == 1) o += 12 * V * ts;
   off[7] = o;
   return o;
 }
@@ -729,6 +763,8 @@ fftevp_status fftevp_set_material(fftevp_ctx* ctx, const fftevp_cubic* c, const 
   return FFTEVP_OK;
 }
 
+static fftevp_status mr_reset(fftevp_ctx* ctx);
+
 fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat, const double* rho) {
   if (!ctx || !quat || !rho) return fail(ctx, FFTEVP_EINVAL, "null argument");
   const size_t V = ctx->V;
@@ -765,7 +801,63 @@ fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat, con
   ctx->last_iters = 0;
   ctx->have_micro = true;
   ctx->state_ok = true;
+  if (ctx->law == 1) return mr_reset(ctx);
   return FFTEVP_OK;
+}
+
+// paper's law: SSD densities from the voxel densities (equal split over the
+// 12 systems) and their parameters
+static fftevp_status mr_reset(fftevp_ctx* ctx) {
+  const size_t V = ctx->V;
+  HIPCHK(ctx->prec == FFTEVP_FP64
+             ? launch_split12<double>((const double*)ctx->b.rho, (double*)ctx->b.ssd, V, ctx->stream)
+             : launch_split12<float>((const float*)ctx->b.rho, (float*)ctx->b.ssd, V, ctx->stream));
+  HIPCHK(mr_params(ctx));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_set_law(fftevp_ctx* ctx, int law, const fftevp_mr* p) {
+  if (!ctx) return FFTEVP_EINVAL;
+  if (law == 0) {
+    ctx->law = 0;
+    return FFTEVP_OK;
+  }
+  if (law != 1 || !p) return fail(ctx, FFTEVP_EINVAL, "law must be 0 (power) or 1 (paper's law, with constants)");
+  if (!ctx->have_mat || !ctx->have_micro)
+    return fail(ctx, FFTEVP_ESTATE, "set_material and set_microstructure must come first");
+  const double v[13] = {p->T, p->Q_slip, p->Q_bulk, p->c1, p->c2, p->c3, p->c4,
+                        p->c5, p->c6, p->c7, p->c8, p->nu_D, p->poisson};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(ctx, FFTEVP_EINVAL, "non-finite constant");
+  if (!(p->T > 0 && p->Q_slip > 0 && p->Q_bulk > 0 && p->c1 > 0 && p->c2 > 0 && p->c3 > 0 && p->c4 >= 0 &&
+        p->c5 >= 0 && p->c6 >= 0 && p->c7 >= 0 && p->c8 > 0 && p->nu_D > 0 && p->poisson > -1 && p->poisson < 0.5 &&
+        ctx->flow.mu > 0 && ctx->flow.b > 0))
+    return fail(ctx, FFTEVP_EINVAL, "constants out of range");
+  const size_t V = ctx->V, ts = ctx->tsize;
+  hipError_t e = hipSuccess;
+  if (!ctx->b.ssd) e = hipMalloc(&ctx->b.ssd, 12 * V * ts);
+  if (e == hipSuccess && !ctx->b.sysp) e = hipMalloc(&ctx->b.sysp, 36 * V * ts);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
+  }
+  const double kB = 1.380649e-23, kT = kB * p->T, mu = ctx->flow.mu, b = ctx->flow.b, mu_pa = mu * 1e6;
+  MrConst c{};
+  c.tp_c = p->c1 * mu * b;
+  c.tc_c = p->Q_slip / (p->c2 * p->c3 * b * b) * 1e-6;
+  c.a_c = 2.0 * kT / (p->c1 * p->c3 * mu_pa * b * b) * p->nu_D * std::exp(-p->Q_slip / kT);
+  c.c4 = p->c4;
+  c.c5 = p->c5;
+  c.c6 = p->c6;
+  c.c8 = p->c8;
+  c.rhom_c = 2.0 * kT / (p->c1 * p->c2 * p->c3 * mu_pa * b * b * b);
+  c.dd_c = std::sqrt(3.0) * mu * b / (16.0 * M_PI * (1.0 - p->poisson));
+  c.climb_c = p->c7 * std::exp(-p->Q_bulk / kT) / kT * 1e6;
+  ctx->mr = *p;
+  ctx->mrc = c;
+  ctx->law = 1;
+  return mr_reset(ctx);
 }
 
 fftevp_status fftevp_set_gnd(fftevp_ctx* ctx, const int* grain_dev, double l0, double xi) {
@@ -860,6 +952,10 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
     case FFTEVP_FIELD_RHO: e = exp(ctx->b.rho, 1, 0); break;
     case FFTEVP_FIELD_SIGMA_ITER: e = exp(ctx->b.sig[ctx->sw], 6, 1); break;
     case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->e_last); break;
+    case FFTEVP_FIELD_RHO_SSD:
+      if (ctx->law != 1) return fail(ctx, FFTEVP_ESTATE, "per-system SSD densities need the paper's law");
+      e = exp(ctx->b.ssd, 12, 0);
+      break;
     case FFTEVP_FIELD_RHO_GNDS:
     case FFTEVP_FIELD_RHO_GNDET:
       if (!ctx->gnd_on) return fail(ctx, FFTEVP_ESTATE, "GND densities are not tracked (fftevp_set_gnd)");
@@ -876,6 +972,13 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
       m.tau0 = ctx->flow.tau0;
       m.taylor = ctx->flow.alpha * ctx->flow.mu * ctx->flow.b;
       const void* sg = ctx->b.sig[ctx->sc];
+      if (ctx->law == 1) {
+        e = dbl ? launch_gdot_mr<double>((const double*)sg, (const double*)ctx->b.quat,
+                                         (const double*)ctx->b.sysp, dst, V, ctx->stream)
+                : launch_gdot_mr<float>((const float*)sg, (const float*)ctx->b.quat, (const float*)ctx->b.sysp,
+                                        dst, V, ctx->stream);
+        break;
+      }
       e = dbl ? launch_gdot<double>((const double*)sg, (const double*)ctx->b.quat, (const double*)ctx->b.rho, dst, V,
                                     m, ctx->flow.gdot0, ctx->stream)
               : launch_gdot<float>((const float*)sg, (const float*)ctx->b.quat, (const float*)ctx->b.rho, dst, V, m,
@@ -912,6 +1015,7 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   hdr[13] = ctx->last_iters;
   hdr[14] = ctx->gnd_on ? 1.0 : 0.0;
   hdr[15] = ctx->leff;
+  hdr[16] = ctx->law;
   char* d = (char*)dst;
   HIPCHK(hipMemcpyAsync(d, hdr, sizeof hdr, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(d + off[0], ctx->b.epsp, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -925,6 +1029,8 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
     HIPCHK(hipMemcpyAsync(d + off[5] + 12 * V * ts, ctx->b.gndet, 12 * V * ts, hipMemcpyDeviceToDevice,
                           ctx->stream));
   }
+  if (ctx->law == 1)
+    HIPCHK(hipMemcpyAsync(d + off[6], ctx->b.ssd, 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FFTEVP_OK;
 }
@@ -939,7 +1045,7 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   HIPCHK(hipMemcpyAsync(hdr, s, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
-      hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0))
+      hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0) || hdr[16] != (double)ctx->law)
     return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
   HIPCHK(hipMemcpyAsync(ctx->b.epsp, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.rho, s + off[1], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -952,6 +1058,10 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
     HIPCHK(hipMemcpyAsync(ctx->b.gndet, s + off[5] + 12 * V * ts, 12 * V * ts, hipMemcpyDeviceToDevice,
                           ctx->stream));
     ctx->leff = hdr[15];
+  }
+  if (ctx->law == 1) {
+    HIPCHK(hipMemcpyAsync(ctx->b.ssd, s + off[6], 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(mr_params(ctx));
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < 6; ++k) ctx->E[k] = hdr[5 + k];
@@ -994,6 +1104,7 @@ fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
     return fail(ctx, FFTEVP_ESTATE, "set_material, set_microstructure and set_loading must come first");
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(g[k])) return fail(ctx, FFTEVP_EINVAL, "non-finite dL/dSigma");
+  if (ctx->law != 0) return fail(ctx, FFTEVP_EINVAL, "the adjoint covers the power law only");
   const fftevp_opts o = resolve_opts(ctx, opts);
   return ctx->prec == FFTEVP_FP64 ? adjoint_impl<double>(ctx, o, before, after, g, adj, dth)
                                   : adjoint_impl<float>(ctx, o, before, after, g, adj, dth);

@@ -55,6 +55,23 @@ struct Mat {
   double qtol;            // full Newton steps below this are final (quadratic regime)
   double tau0, taylor;    // tauc = tau0 + taylor * sqrt(rho), taylor = alpha mu b
   double inv_n0;          // 1 / n0
+  double dt;              // time increment (s)
+};
+
+// Flow rules of the local solve: the power law with a general or an integral
+// exponent, or the paper's dislocation-based law (Sec. 2.2, Eq. 3) with
+// per-system parameters frozen over the increment.
+enum { FLOW_POWER = 0, FLOW_POWER_INT = 1, FLOW_MR = 2 };
+
+// Per-voxel parameters of the paper's law, stored [3][12][V]:
+// tau_pass (MPa), tau_cut (MPa), A = gdot_0 exp(-Q_slip / kB T) (1/s).
+template <typename T>
+struct SysParams {
+  const T* p;
+  size_t V, g;
+  __device__ __forceinline__ T tp(int a) const { return p[(size_t)a * V + g]; }
+  __device__ __forceinline__ T tc(int a) const { return p[(size_t)(12 + a) * V + g]; }
+  __device__ __forceinline__ T amp(int a) const { return p[(size_t)(24 + a) * V + g]; }
 };
 
 template <typename T>
@@ -281,6 +298,67 @@ __device__ __forceinline__ void flow_type(const T (&s)[6], T cn, T cs, T n, int 
   g[3 + slot_q(TT)] += gs0 - gs1;
 }
 
+// The paper's flow rule for the four systems of a type: with
+// x = (|tau| - tau_pass) / tau_cut > 0, gdot = A sinh(x) sign(tau), Jacobian
+// weight dgdot/dtau = A cosh(x) / tau_cut and potential A tau_cut (cosh x - 1)
+// (zero below the passing stress). g, visc and asum as for the power law, in
+// rate units (the residual then takes dt instead of dt gdot0).
+template <int TT, typename T, typename W>
+__device__ __forceinline__ void flow_type_mr(const T (&s)[6], const SysParams<T>& sp, W (&w)[12], T (&g)[6],
+                                             T& visc, T& asum) {
+  T x[4];
+  resolved_type<TT>(s, T(kUN), T(kUS), x);
+  T gn = T(-0.0), gs0 = T(-0.0), gs1 = T(-0.0);
+  static_for<0, 12>([&](auto ac) {
+    constexpr int A = decltype(ac)::value;
+    if constexpr (ntype(A) == TT) {
+      constexpr int j = tpos(A);
+      const T tcut = sp.tc(A), amp = sp.amp(A);
+      const T xx = (fabs(x[j]) - sp.tp(A)) / tcut;
+      T rate = T(0), wa = T(0), psi = T(0);
+      if (xx > T(0)) {
+        const T ex = exp(xx), iex = T(1) / ex;
+        const T sh = T(0.5) * (ex - iex), ch = T(0.5) * (ex + iex);
+        rate = amp * sh;
+        wa = amp * ch / tcut;
+        psi = amp * tcut * (ch - T(1));
+      }
+      w[A] = W(wa);
+      visc += psi;
+      asum += rate;
+      const T sp_ = x[j] < T(0) ? -rate : rate;
+      if constexpr (nsgn(A) > 0) gn += sp_;
+      else gn -= sp_;
+      if constexpr (srho(A) > 0) {
+        if constexpr (ssgn(A) > 0) gs0 += sp_;
+        else gs0 -= sp_;
+      } else {
+        if constexpr (ssgn(A) > 0) gs1 += sp_;
+        else gs1 -= sp_;
+      }
+    }
+  });
+  static_for<0, 3>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    if constexpr (dcomp(TT, I) > 0) g[I] += gn;
+    else if constexpr (dcomp(TT, I) < 0) g[I] -= gn;
+  });
+  g[3 + slot_p(TT)] += gs0 + gs1;
+  g[3 + slot_q(TT)] += gs0 - gs1;
+}
+
+template <typename T, typename W>
+__device__ __forceinline__ void flow_eval_mr(const T (&s)[6], const SysParams<T>& sp, W (&w)[12], T (&g)[6],
+                                             T& visc, T& asum) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = T(-0.0);
+  visc = T(-0.0);
+  asum = T(-0.0);
+  flow_type_mr<0>(s, sp, w, g, visc, asum);
+  flow_type_mr<1>(s, sp, w, g, visc, asum);
+  flow_type_mr<2>(s, sp, w, g, visc, asum);
+}
+
 template <bool INTN, typename T, typename W>
 __device__ __forceinline__ void flow_eval(const T (&s)[6], T itauc, T n, int n_int, W (&w)[12],
                                           T (&g)[6], T& visc, T& asum) {
@@ -307,18 +385,21 @@ __device__ __forceinline__ void cubic_mul(T d, T o, T sh, const T (&v)[6], T (&o
 
 // residual and potential of the local problem in the crystal frame:
 //   r   = A s - b + c1 * m(g)
-//   phi = 1/2 s.A s - b.s + c1 tauc/(n+1) visc
+//   phi = 1/2 s.A s - b.s + c1 tauc/(n+1) visc   (power law, c1 = dt gdot0)
+//   phi = 1/2 s.A s - b.s + dt visc              (paper's law, c1 = dt)
 // The residual is formed in T (it cancels large terms); once formed it is
 // returned in FP32 with the Jacobian weights w: the Newton direction is an
 // FP32 solve, and rounding a small residual keeps its relative precision.
-template <bool INTN, typename T>
+template <int FLOW, typename T>
 __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], const T (&b)[6],
-                                               T tauc, T itauc, float (&w)[12], float (&r)[6], T& phi) {
+                                               T tauc, T itauc, float (&w)[12], float (&r)[6], T& phi,
+                                               const SysParams<T>& sp) {
   T g[6], visc, asum;
-  flow_eval<INTN>(s, itauc, T(M.n), M.n_int, w, g, visc, asum);
+  if constexpr (FLOW == FLOW_MR) flow_eval_mr(s, sp, w, g, visc, asum);
+  else flow_eval<FLOW == FLOW_POWER_INT>(s, itauc, T(M.n), M.n_int, w, g, visc, asum);
   T As[6];
   cubic_mul(T(M.a_d), T(M.a_o), T(M.a_s), s, As);
-  const T c1 = T(M.c1);
+  const T c1 = FLOW == FLOW_MR ? T(M.dt) : T(M.c1);
   T q = T(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -326,7 +407,8 @@ __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], co
     r[k] = float(As[k] - b[k] + c1 * u * g[k]);
     q += s[k] * (T(0.5) * As[k] - b[k]);
   }
-  phi = q + c1 * tauc / (T(M.n) + T(1)) * visc;
+  if constexpr (FLOW == FLOW_MR) phi = q + c1 * visc;
+  else phi = q + c1 * tauc / (T(M.n) + T(1)) * visc;
 }
 
 // J = A + cj * sum_a w_a m_a m_a^T  (packed lower triangle, 21 entries),

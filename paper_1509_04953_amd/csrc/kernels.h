@@ -62,6 +62,7 @@ struct LocalArgs {
   const T* rho;         // density, [V]
   const T* quat;        // orientation, [4][V]
   const T* sig_t;       // tangent mode: stress the tangent is taken at
+  const T* sysp;        // paper's flow rule: per-system parameters [3][12][V]; null: power law
   double* partial;      // [NPART][blocks]
   const Ctl* ctl;
   const cx<T>* tw;      // twiddles for n0
@@ -112,6 +113,16 @@ struct GndArgs {
   double dt, inv_b, inv_h;  // increment, 1/b (1/m), 1/l_eff (1/m)
 };
 
+// Constants of the paper's law (Sec. 2.2, Eq. 3-6), SI with stresses in MPa:
+//   tau_pass = tp_c sqrt(rho_P), tau_cut = tc_c sqrt(rho_F), A = a_c sqrt(rho_P),
+//   rho_M = rhom_c sqrt(rho_P rho_F), d_dipole = dd_c / |tau|,
+//   climb term = climb_c sigma_vm rho_SSD^2 gdot_vm^c8.
+struct MrConst {
+  double tp_c, tc_c, a_c;
+  double c4, c5, c6, c8;
+  double rhom_c, dd_c, climb_c;
+};
+
 template <typename T>
 struct StateArgs {
   const T* sig;
@@ -123,6 +134,13 @@ struct StateArgs {
   size_t nvox;
   double dt, gdot0, k1, k2;
   Mat m;
+  // paper's law: per-system SSD densities (in/out) and frozen parameters;
+  // GND densities enter the forest/parallel projections when tracked
+  T* ssd;             // [12][V]
+  const T* sysp;      // [3][12][V]
+  const T* gnds;      // [12][V] or null
+  const T* gndet;     // [12][V] or null
+  MrConst mr;
 };
 
 // scalar parameters of the adjoint kernels
@@ -166,6 +184,16 @@ hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, s
                        double gdot0, hipStream_t s);
 template <typename T>
 hipError_t launch_gnd(const GndArgs<T>& a, hipStream_t s);
+// paper's law: end-of-increment update, per-system parameters, slip rates
+template <typename T>
+hipError_t launch_state_mr(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
+template <typename T>
+hipError_t launch_split12(const T* rho, T* ssd, size_t V, hipStream_t s);
+template <typename T>
+hipError_t launch_mr_params(const T* ssd, const T* gnds, const T* gndet, T* sysp, size_t V, const MrConst& c,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_gdot_mr(const T* sig, const T* quat, const T* sysp, double* out, size_t V, hipStream_t s);
 template <typename T>
 hipError_t launch_ingest(const double* q, const double* rho, T* qo, T* ro, size_t V, double* partial,
                          int nblocks, double* out2, hipStream_t s);

@@ -169,9 +169,10 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
 #define FFTEVP_LOCAL_WAVES_F32 4
 #endif
 
-// INTN: the rate exponent is a positive integer (compile-time choice of the
-// power evaluation; the host picks the instance).
-template <typename T, int N0, int MODE, bool INTN>
+// FLOW: the flow rule (FLOW_POWER, FLOW_POWER_INT when the rate exponent is
+// a positive integer, FLOW_MR for the paper's law; the host picks the
+// instance).
+template <typename T, int N0, int MODE, int FLOW>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32) void k_local(
     LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
@@ -278,7 +279,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
       T phi = T(0);
       float slope = 0.f, rn2 = 0.f;
       T step = T(0);
-      const float cj = float(T(M.c1) * T(M.n) * itauc);
+      const float cj = FLOW == FLOW_MR ? float(M.dt) : float(T(M.c1) * T(M.n) * itauc);
+      const SysParams<T> sp{a.sysp, vox, g};
       const T ntol2 = T(M.ntol) * T(M.ntol), qtol2 = T(M.qtol) * T(M.qtol);
       bool conv = false, first = true;
 #pragma unroll
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
         T phi1, cand[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * T(d[k]);
-        local_residual<INTN>(M, cand, b, tauc, itauc, w, r, phi1);
+        local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, sp);
         float rn1 = 0.f;
 #pragma unroll
         for (int k = 0; k < 6; ++k) rn1 += r[k] * r[k];
@@ -356,7 +358,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_L
 #pragma unroll
       for (int k = 0; k < 6; ++k) st[k] = a.sig_t[(size_t)k * vox + g];
       to_crystal(R, st, stc);
-      flow_eval<INTN>(stc, itauc, T(M.n), M.n_int, w, g6, visc, asum);
+      static_assert(FLOW != FLOW_MR, "tangent solves use the power law");
+      flow_eval<FLOW == FLOW_POWER_INT>(stc, itauc, T(M.n), M.n_int, w, g6, visc, asum);
       local_jacobian<T>(M, w, T(M.c1) * T(M.n) * itauc, J);
       ldl_solve(J, b, sc);
       nit = 1;
@@ -905,6 +908,170 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// the paper's dislocation-based law (Sec. 2.2, Eq. 3-6)
+// ---------------------------------------------------------------------------
+// |cos| and |sin| of the angles (n_a, t_b) and (n_a, d_b) from the integer
+// vectors: |n.t| = k / sqrt18 (k <= 4), |n.d| = k / sqrt6 (k <= 2).
+struct ProjTab {
+  double cnt[12][12], snt[12][12], cnd[12][12], snd[12][12];
+};
+__host__ __device__ constexpr ProjTab make_proj_tab() {
+  // k / sqrt18 and sqrt(18 - k^2) / sqrt18, k = 0..4
+  const double c18[5] = {0.0, 0.23570226039551584147, 0.47140452079103168293, 0.70710678118654752440,
+                         0.94280904158206336587};
+  const double s18[5] = {1.0, 0.97182531580755005857, 0.88191710368819698821, 0.70710678118654752440,
+                         0.33333333333333333333};
+  // k / sqrt6 and sqrt(6 - k^2) / sqrt6, k = 0..2
+  const double c6[3] = {0.0, 0.40824829046386301637, 0.81649658092772603273};
+  const double s6[3] = {1.0, 0.91287092917527685576, 0.57735026918962576451};
+  ProjTab t{};
+  for (int a = 0; a < 12; ++a)
+    for (int b = 0; b < 12; ++b) {
+      int nt = kN[a][0] * kT[b][0] + kN[a][1] * kT[b][1] + kN[a][2] * kT[b][2];
+      int nd = kN[a][0] * kD[b][0] + kN[a][1] * kD[b][1] + kN[a][2] * kD[b][2];
+      nt = nt < 0 ? -nt : nt;
+      nd = nd < 0 ? -nd : nd;
+      t.cnt[a][b] = c18[nt];
+      t.snt[a][b] = s18[nt];
+      t.cnd[a][b] = c6[nd];
+      t.snd[a][b] = s6[nd];
+    }
+  return t;
+}
+__device__ constexpr ProjTab kProj = make_proj_tab();
+
+// forest and parallel densities (Eq. 4-5) of the 12 systems of voxel g
+template <typename T>
+__device__ __forceinline__ void mr_projections(const T* __restrict__ ssd, const T* __restrict__ gs,
+                                               const T* __restrict__ ge, size_t V, size_t g, double (&F)[12],
+                                               double (&P)[12]) {
+  double r[12], rs[12], re[12];
+#pragma unroll
+  for (int b = 0; b < 12; ++b) {
+    r[b] = ssd[(size_t)b * V + g];
+    rs[b] = gs ? fabs((double)gs[(size_t)b * V + g]) : 0.0;
+    re[b] = ge ? fabs((double)ge[(size_t)b * V + g]) : 0.0;
+  }
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    double f = 0.0, p = 0.0;
+#pragma unroll
+    for (int b = 0; b < 12; ++b) {
+      f += (r[b] + re[b]) * kProj.cnt[a][b] + rs[b] * kProj.cnd[a][b];
+      p += (r[b] + re[b]) * kProj.snt[a][b] + rs[b] * kProj.snd[a][b];
+    }
+    F[a] = f;
+    P[a] = p;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mr_params(const T* __restrict__ ssd, const T* __restrict__ gs,
+                                                   const T* __restrict__ ge, T* __restrict__ sysp, size_t V,
+                                                   MrConst c) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double F[12], P[12];
+    mr_projections(ssd, gs, ge, V, g, F, P);
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      const double sp = sqrt(P[a]);
+      sysp[(size_t)a * V + g] = (T)(c.tp_c * sp);
+      sysp[(size_t)(12 + a) * V + g] = (T)(c.tc_c * sqrt(F[a]));
+      sysp[(size_t)(24 + a) * V + g] = (T)(c.a_c * sp);
+    }
+  }
+}
+
+// slip rate of system a at resolved shear tau (FP64)
+template <typename T>
+__device__ __forceinline__ double mr_rate(const SysParams<T>& sp, int a, double tau) {
+  const double xx = (fabs(tau) - (double)sp.tp(a)) / (double)sp.tc(a);
+  if (!(xx > 0.0)) return 0.0;
+  const double ex = exp(xx);
+  const double r = (double)sp.amp(a) * 0.5 * (ex - 1.0 / ex);
+  return tau < 0.0 ? -r : r;
+}
+
+// end of an increment with the paper's law: slip rates at the converged
+// stress (parameters of the increment's start), plastic strain, SSD
+// densities (Eq. 6, explicit), their sum as the voxel density
+template <typename T>
+__global__ __launch_bounds__(256) void k_state_mr(StateArgs<T> a) {
+  const size_t V = a.nvox;
+  double part[2] = {0.0, 0.0};
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double R[9], s[6], sc[6];
+    quat_rot<double>(a.quat[g], a.quat[V + g], a.quat[2 * V + g], a.quat[3 * V + g], R);
+    for (int k = 0; k < 6; ++k) s[k] = a.sig[k * V + g];
+    to_crystal(R, s, sc);
+    const SysParams<T> sp{a.sysp, V, g};
+    double tau[12], gd[12], gk[6] = {0, 0, 0, 0, 0, 0}, gsum = 0.0;
+    static_for<0, 12>([&](auto ac) {
+      constexpr int A = decltype(ac)::value;
+      tau[A] = resolved<A>(sc);
+      gd[A] = mr_rate(sp, A, tau[A]);
+      gsum += fabs(gd[A]);
+      static_for<0, 6>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        acc_sign<kSign[A][K]>(gk[K], gd[A]);
+      });
+    });
+    double dpc[6], dp[6], ep2 = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      dpc[k] = (k < 3 ? kUN : kUS) * gk[k];
+      ep2 += dpc[k] * dpc[k];
+    }
+    to_sample(R, dpc, dp);
+    for (int k = 0; k < 6; ++k) a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
+    // von Mises stress and equivalent plastic rate (frame invariant)
+    const double tr = (sc[0] + sc[1] + sc[2]) / 3.0;
+    double s2 = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      const double dv = sc[k] - (k < 3 ? tr : 0.0);
+      s2 += dv * dv;
+    }
+    const double svm = sqrt(1.5 * s2), gvm = sqrt(2.0 / 3.0 * ep2);
+    const double climb_f = a.mr.climb_c * svm * (gvm > 0.0 ? pow(gvm, a.mr.c8) : 0.0);
+    double F[12], P[12];
+    mr_projections(a.ssd, a.gnds, a.gndet, V, g, F, P);
+    double tot = 0.0;
+#pragma unroll
+    for (int al = 0; al < 12; ++al) {
+      const double rho = a.ssd[(size_t)al * V + g];
+      const double ag = fabs(gd[al]);
+      const double rhom = a.mr.rhom_c * sqrt(P[al] * F[al]);
+      const double ddip = ag > 0.0 ? a.mr.dd_c / fabs(tau[al]) : 0.0;
+      const double rate = a.mr.c4 * sqrt(F[al]) * ag + a.mr.c6 * ddip * rhom * ag - a.mr.c5 * rho * ag -
+                          climb_f * rho * rho;
+      const double rn = rho + a.dt * rate;
+      a.ssd[(size_t)al * V + g] = (T)rn;
+      tot += (double)(T)rn;
+      if (a.gd) a.gd[(size_t)al * V + g] = (T)gd[al];
+    }
+    a.rho[g] = (T)tot;
+    part[0] += (double)(T)tot;
+    part[1] += gsum;
+  }
+  block_reduce<2, 0>(part, a.partial + (size_t)blockIdx.x * 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gdot_mr(const T* __restrict__ sig, const T* __restrict__ quat,
+                                                 const T* __restrict__ sysp, double* __restrict__ out, size_t V) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    double R[9], s[6], sc[6];
+    quat_rot<double>(quat[g], quat[V + g], quat[2 * V + g], quat[3 * V + g], R);
+    for (int k = 0; k < 6; ++k) s[k] = sig[k * V + g];
+    to_crystal(R, s, sc);
+    const SysParams<T> sp{sysp, V, g};
+    static_for<0, 12>([&](auto ac) {
+      constexpr int A = decltype(ac)::value;
+      out[(size_t)A * V + g] = mr_rate(sp, A, resolved<A>(sc));
+    });
+  }
+}
+
 __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ p, int n, double* out) {
   double v[2] = {0.0, 0.0};
   for (int b = threadIdx.x; b < n; b += 256) {
@@ -1122,10 +1289,16 @@ hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s) {
 #define FFTEVP_LOCAL(N)                                                                       \
   case N: {                                                                                   \
     const int lpb = LocalShape<T, N>::LPB;                                                    \
+    if constexpr (MODE == MODE_NEWTON) {                                                      \
+      if (a.sysp) {                                                                           \
+        hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_MR>), dim3(planes / lpb), dim3(256), 0, s, a); \
+        break;                                                                                \
+      }                                                                                       \
+    }                                                                                         \
     if (MODE == MODE_EXPORT || a.m.n_int > 0)                                                 \
-      hipLaunchKernelGGL((k_local<T, N, MODE, true>), dim3(planes / lpb), dim3(256), 0, s, a);  \
+      hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_POWER_INT>), dim3(planes / lpb), dim3(256), 0, s, a); \
     else                                                                                      \
-      hipLaunchKernelGGL((k_local<T, N, MODE, false>), dim3(planes / lpb), dim3(256), 0, s, a); \
+      hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_POWER>), dim3(planes / lpb), dim3(256), 0, s, a); \
     break;                                                                                    \
   }
   switch (n0) {
@@ -1216,6 +1389,40 @@ hipError_t launch_gdot(const T* sig, const T* quat, const T* rho, double* out, s
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_split12(const T* __restrict__ rho, T* __restrict__ ssd, size_t V) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    const T r = (T)((double)rho[g] / 12.0);
+    for (int a = 0; a < 12; ++a) ssd[(size_t)a * V + g] = r;
+  }
+}
+
+template <typename T>
+hipError_t launch_split12(const T* rho, T* ssd, size_t V, hipStream_t s) {
+  hipLaunchKernelGGL(k_split12<T>, dim3(grid_for(V)), dim3(256), 0, s, rho, ssd, V);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_state_mr(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_mr<T>, dim3(nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, (const double*)a.partial, nblocks, out2);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mr_params(const T* ssd, const T* gnds, const T* gndet, T* sysp, size_t V, const MrConst& c,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_params<T>, dim3(grid_for(V)), dim3(256), 0, s, ssd, gnds, gndet, sysp, V, c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gdot_mr(const T* sig, const T* quat, const T* sysp, double* out, size_t V, hipStream_t s) {
+  hipLaunchKernelGGL(k_gdot_mr<T>, dim3(grid_for(V)), dim3(256), 0, s, sig, quat, sysp, out, V);
+  return hipGetLastError();
+}
+
 // GND update of one increment from the slip rates k_state left in gd.
 template <typename T>
 hipError_t launch_gnd(const GndArgs<T>& a, hipStream_t s) {
@@ -1265,6 +1472,11 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_gdot<T>(const T*, const T*, const T*, double*, size_t, const Mat&, double, \
                                      hipStream_t);                                            \
   template hipError_t launch_gnd<T>(const GndArgs<T>&, hipStream_t);                          \
+  template hipError_t launch_state_mr<T>(const StateArgs<T>&, int, double*, hipStream_t);      \
+  template hipError_t launch_split12<T>(const T*, T*, size_t, hipStream_t);                   \
+  template hipError_t launch_mr_params<T>(const T*, const T*, const T*, T*, size_t, const MrConst&, \
+                                          hipStream_t);                                       \
+  template hipError_t launch_gdot_mr<T>(const T*, const T*, const T*, double*, size_t, hipStream_t); \
   template hipError_t launch_ingest<T>(const double*, const double*, T*, T*, size_t, double*, int, \
                                        double*, hipStream_t);                                  \
   template hipError_t launch_export<T>(const T*, double*, size_t, int, int, hipStream_t);      \

@@ -19,15 +19,20 @@ _lib = None
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENONFINITE, ELOCAL, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5, "gdot": 6,
-          "rho_gnds": 7, "rho_gndet": 8}
+          "rho_gnds": 7, "rho_gndet": 8, "rho_ssd": 9}
 NPROF = 8
 PROF_NAMES = ("local", "unused", "yfwd", "zgamma", "yinv", "state", "adjoint", "gnd")
 NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6, "gdot": 12,
-         "rho_gnds": 12, "rho_gndet": 12}
+         "rho_gnds": 12, "rho_gndet": 12, "rho_ssd": 12}
 
 
 class Cubic(C.Structure):
     _fields_ = [("C11", C.c_double), ("C12", C.c_double), ("C44", C.c_double)]
+
+
+class MRC(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("T", "Q_slip", "Q_bulk", "c1", "c2", "c3", "c4", "c5", "c6",
+                                          "c7", "c8", "nu_D", "poisson")]
 
 
 class FlowC(C.Structure):
@@ -67,6 +72,7 @@ def library():
         "fftevp_set_microstructure": (I, [P, P, P]),
         "fftevp_set_loading": (I, [P, C.POINTER(LoadingC)]),
         "fftevp_set_gnd": (I, [P, P, C.c_double, C.c_double]),
+        "fftevp_set_law": (I, [P, I, C.POINTER(MRC)]),
         "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_get_field": (I, [P, I, P]),
         "fftevp_state_bytes": (S, [P]),
@@ -91,6 +97,25 @@ class FftevpError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fftevp status {status}: {msg}")
         self.status = status
+
+
+@dataclass
+class MaRoters:
+    """Constants of the paper's dislocation-based law (Table 1; T, nu_D and
+    the Poisson ratio as documented in include/fftevp.h)."""
+    T: float = 473.0
+    Q_slip: float = 3.3e-19
+    Q_bulk: float = 3.51e-19
+    c1: float = 0.5
+    c2: float = 3.0
+    c3: float = 3.0
+    c4: float = 8.0e7
+    c5: float = 10.0
+    c6: float = 3.0e10
+    c7: float = 7.0e-28
+    c8: float = 0.24
+    nu_D: float = 1.0e13
+    poisson: float = 0.34
 
 
 @dataclass
@@ -200,6 +225,14 @@ class Solver:
         r = self._dev(rho, (self.nvox,))
         self._check(self.lib.fftevp_set_microstructure(self.h, C.c_void_p(q.data_ptr()),
                                                        C.c_void_p(r.data_ptr())))
+
+    def set_law(self, law: "MaRoters | None"):
+        """None: the power law; a MaRoters instance: the paper's law."""
+        if law is None:
+            self._check(self.lib.fftevp_set_law(self.h, 0, None))
+            return
+        c = MRC(*(getattr(law, k) for k, _ in MRC._fields_))
+        self._check(self.lib.fftevp_set_law(self.h, 1, C.byref(c)))
 
     def set_gnd(self, grains, l0: float = 21.4e-6, xi: float = 200.0):
         """Track GND densities (screw and edge, per slip system) from every
