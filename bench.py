@@ -152,6 +152,44 @@ def run_gnd(w, quat, rho, grains, precision, increments=4):
             "l_eff_m": r.l_eff}
 
 
+def run_mr(w, quat, rho, precision, steps=3, warmup=1):
+    """The paper's own flow rule and SSD evolution (Sec. 2.2, Eq. 3-6) on the
+    same workload (initial SSD density 2.5e12 m^-2 per voxel scaled by the
+    workload's log-normal field): voxel-iterations/s, iterations per
+    increment and the local kernel's HBM rate. Its algorithmic bytes per
+    voxel: the power-law kernel's 35 words minus the density plus 36 words of
+    per-system parameters (tau_pass, 1/tau_cut, prefactor)."""
+    import torch
+    from paper_1509_04953_amd import Solver, Material, MaRoters, Load, Opts
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(quat, rho * 2.5)
+    s.set_loading(Load(dt=w.dt))
+    s.set_law(MaRoters())
+    opts = Opts(tol=w.tol, max_iter=3000)
+    for _ in range(warmup):
+        s.step(opts)
+    s.set_profiling(True, classes=("local",))
+    s.profile(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(steps):
+        r = s.step(opts)
+        iters.append(r.iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms, n = s.profile(reset=True)["local"]
+    s.close()
+    word = 8 if precision == "fp64" else 4
+    nbytes = (35 - 1 + 36) * w.voxels * word + 12 * w.shape[1] * w.shape[2] * word
+    avg = ms / max(n, 1)
+    return {"precision": precision, "value": sum(iters) * w.voxels / dt, "unit": "voxel-iterations/s",
+            "iters_per_increment": float(np.mean(iters)), "s33_last": float(r.Sigma[2]),
+            "local_avg_ms": avg, "local_GBps": nbytes / (avg * 1e-3) / 1e9,
+            "local_frac_hbm": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def source_hash():
     """Prefix of the sha256 of the device sources (matches the profiles)."""
     import hashlib
@@ -278,6 +316,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-gnd", action="store_true")
+    ap.add_argument("--no-mr", action="store_true")
     ap.add_argument("--adjoint-workload", default="cu128adj")
     ap.add_argument("--adjoint-increments", type=int, default=0,
                     help="increments of the adjoint run (default: the workload's)")
@@ -344,6 +383,8 @@ def main():
                                                        / np.max(np.abs(r["s33"])))}
     if not args.no_gnd:
         line["gnd"] = run_gnd(w, quat, rho, grains, precs[0])
+    if not args.no_mr:
+        line["paper_law"] = {p: run_mr(w, quat, rho, p) for p in precs}
     if not args.no_adjoint:
         wa = synth.workload(args.adjoint_workload)
         if wa.name == w.name:

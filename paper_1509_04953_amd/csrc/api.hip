@@ -38,7 +38,7 @@ struct Bufs {
   void* gndet = nullptr;   // edge GND density per system, [12][V]
   // the paper's law (allocated by set_law)
   void* ssd = nullptr;     // SSD density per system, [12][V]
-  void* sysp = nullptr;    // tau_pass, tau_cut, A per system, [3][12][V]
+  void* sysp = nullptr;    // tau_pass, 1/tau_cut, A per system, [3][12][V]
 };
 
 }  // namespace

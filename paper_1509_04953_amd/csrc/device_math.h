@@ -63,16 +63,24 @@ struct Mat {
 // per-system parameters frozen over the increment.
 enum { FLOW_POWER = 0, FLOW_POWER_INT = 1, FLOW_MR = 2 };
 
-// Per-voxel parameters of the paper's law, stored [3][12][V]:
-// tau_pass (MPa), tau_cut (MPa), A = gdot_0 exp(-Q_slip / kB T) (1/s).
+// Per-voxel parameters of the paper's law, stored [3][12][V]: tau_pass (MPa),
+// 1 / tau_cut (1/MPa), A = gdot_0 exp(-Q_slip / kB T) (1/s); the flow needs
+// no division (tau_cut for the potential comes from a refined reciprocal).
 template <typename T>
 struct SysParams {
   const T* p;
   size_t V, g;
   __device__ __forceinline__ T tp(int a) const { return p[(size_t)a * V + g]; }
-  __device__ __forceinline__ T tc(int a) const { return p[(size_t)(12 + a) * V + g]; }
+  __device__ __forceinline__ T itc(int a) const { return p[(size_t)(12 + a) * V + g]; }
   __device__ __forceinline__ T amp(int a) const { return p[(size_t)(24 + a) * V + g]; }
 };
+
+// 1/x: the hardware reciprocal, refined once by Newton's method in FP64
+__device__ __forceinline__ float fast_recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_recip(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return r * __builtin_fma(-x, r, 2.0);
+}
 
 template <typename T>
 __device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T (&R)[9]) {
@@ -313,15 +321,15 @@ __device__ __forceinline__ void flow_type_mr(const T (&s)[6], const SysParams<T>
     constexpr int A = decltype(ac)::value;
     if constexpr (ntype(A) == TT) {
       constexpr int j = tpos(A);
-      const T tcut = sp.tc(A), amp = sp.amp(A);
-      const T xx = (fabs(x[j]) - sp.tp(A)) / tcut;
+      const T itc = sp.itc(A), amp = sp.amp(A);
+      const T xx = (fabs(x[j]) - sp.tp(A)) * itc;
       T rate = T(0), wa = T(0), psi = T(0);
       if (xx > T(0)) {
-        const T ex = exp(xx), iex = T(1) / ex;
+        const T ex = exp(xx), iex = fast_recip(ex);
         const T sh = T(0.5) * (ex - iex), ch = T(0.5) * (ex + iex);
         rate = amp * sh;
-        wa = amp * ch / tcut;
-        psi = amp * tcut * (ch - T(1));
+        wa = amp * ch * itc;
+        psi = amp * fast_recip(itc) * (ch - T(1));
       }
       w[A] = W(wa);
       visc += psi;

@@ -168,12 +168,19 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
 #ifndef FFTEVP_LOCAL_WAVES_F32
 #define FFTEVP_LOCAL_WAVES_F32 4
 #endif
+// the paper's flow rule holds more per-system state (exp, four parameters)
+#ifndef FFTEVP_MR_WAVES
+#define FFTEVP_MR_WAVES 1
+#endif
+#ifndef FFTEVP_MR_WAVES_F32
+#define FFTEVP_MR_WAVES_F32 2
+#endif
 
 // FLOW: the flow rule (FLOW_POWER, FLOW_POWER_INT when the rate exponent is
 // a positive integer, FLOW_MR for the paper's law; the host picks the
 // instance).
 template <typename T, int N0, int MODE, int FLOW>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32) void k_local(
+__global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_WAVES : FFTEVP_MR_WAVES_F32) : (sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32)) void k_local(
     LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
   if (a.ctl && a.ctl->done) return;
@@ -975,10 +982,10 @@ __global__ __launch_bounds__(256) void k_mr_params(const T* __restrict__ ssd, co
     mr_projections(ssd, gs, ge, V, g, F, P);
 #pragma unroll
     for (int a = 0; a < 12; ++a) {
-      const double sp = sqrt(P[a]);
+      const double sp = sqrt(P[a]), tc = c.tc_c * sqrt(F[a]), amp = c.a_c * sp;
       sysp[(size_t)a * V + g] = (T)(c.tp_c * sp);
-      sysp[(size_t)(12 + a) * V + g] = (T)(c.tc_c * sqrt(F[a]));
-      sysp[(size_t)(24 + a) * V + g] = (T)(c.a_c * sp);
+      sysp[(size_t)(12 + a) * V + g] = (T)(1.0 / tc);
+      sysp[(size_t)(24 + a) * V + g] = (T)amp;
     }
   }
 }
@@ -986,7 +993,7 @@ __global__ __launch_bounds__(256) void k_mr_params(const T* __restrict__ ssd, co
 // slip rate of system a at resolved shear tau (FP64)
 template <typename T>
 __device__ __forceinline__ double mr_rate(const SysParams<T>& sp, int a, double tau) {
-  const double xx = (fabs(tau) - (double)sp.tp(a)) / (double)sp.tc(a);
+  const double xx = (fabs(tau) - (double)sp.tp(a)) * (double)sp.itc(a);
   if (!(xx > 0.0)) return 0.0;
   const double ex = exp(xx);
   const double r = (double)sp.amp(a) * 0.5 * (ex - 1.0 / ex);
