@@ -37,6 +37,7 @@ import numpy as np
 
 from . import local as L
 from .crystal import voxel_material
+from . import drx as DX
 from . import ma_roters as MR
 from .gnd import gnd_rates, next_leff
 from .green import gamma_field, green_apply
@@ -114,6 +115,26 @@ class Oracle:
         """Track GND densities (Sec. 2.2, Eq. 7-8; see oracle.gnd) from now on."""
         self.gnd = dict(grains=np.asarray(grains).reshape(-1).copy(), leff=float(l0), xi=float(xi),
                         rs=np.zeros((12, self.nvox)), ret=np.zeros((12, self.nvox)))
+
+    def enable_drx(self, drx, u0):
+        """DRX nucleation (Sec. 2.3, 2.5; see oracle.drx): draw the nucleation
+        strengths from uniforms u0 (V,). Needs GND tracking (grain ids)."""
+        assert self.gnd is not None, "DRX nucleation needs the grain ids of GND tracking"
+        self.drx = drx
+        self.kappa = DX.weibull_strength(u0, drx.kc, drx.q)
+
+    def drx_nucleate(self, u):
+        """Test every grain-boundary voxel on the current state; returns the
+        number of new nuclei. u: fresh uniforms (V,) for the redraws."""
+        G = self.gnd
+        k = DX.total_density(self.rho, G["rs"], G["ret"], self.mr,
+                             None if self.mr is None else self.ssd)
+        sites = DX.gb_sites(G["grains"], self.shape)
+        hit, self.kappa = DX.nucleate(self.kappa, k, sites, np.asarray(u, dtype=np.float64), self.drx)
+        G["grains"] = np.where(hit, -(np.arange(self.nvox) + 1), G["grains"])
+        G["rs"] = np.where(hit[None], self.drx.s_soften * G["rs"], G["rs"])
+        G["ret"] = np.where(hit[None], self.drx.s_soften * G["ret"], G["ret"])
+        return int(hit.sum())
 
     def enable_mr(self, law=None):
         """Use the paper's own flow rule and SSD evolution (Sec. 2.2, Eq. 3-6;
@@ -236,6 +257,10 @@ class Oracle:
             return mandel_to_voigt(a.T)
         if name == "rho":
             return self.rho.copy()
+        if name == "kappa":
+            return self.kappa.copy()
+        if name == "grain":
+            return self.gnd["grains"].astype(np.float64)
         if name == "rho_ssd":
             return self.ssd.T.copy()
         if name in ("rho_gnds", "rho_gndet"):
