@@ -64,7 +64,9 @@ typedef enum {
   FFTEVP_FIELD_GDOT = 6,        /* slip rates of the 12 systems, 1/s (see below)  */
   FFTEVP_FIELD_RHO_GNDS = 7,    /* screw GND density per system, 12 comps, m^-2   */
   FFTEVP_FIELD_RHO_GNDET = 8,   /* edge GND density per system, 12 comps, m^-2    */
-  FFTEVP_FIELD_RHO_SSD = 9      /* SSD density per system (paper's law), 12 comps */
+  FFTEVP_FIELD_RHO_SSD = 9,     /* SSD density per system (paper's law), 12 comps */
+  FFTEVP_FIELD_KAPPA = 10,      /* DRX nucleation strength, m^-2                  */
+  FFTEVP_FIELD_GRAIN = 11       /* grain ids (as doubles; nuclei negative)        */
 } fftevp_field;
 
 typedef struct fftevp_ctx fftevp_ctx;
@@ -197,6 +199,35 @@ typedef struct {
  * (EINVAL otherwise); snapshots record the law and load only into a
  * context with the same law. */
 fftevp_status fftevp_set_law(fftevp_ctx* ctx, int law, const fftevp_mr* p);
+
+/* DRX nucleation parameters (Table 2): characteristic density kc (m^-2),
+ * Weibull exponent q, kc factor s_nucl for strengths drawn after a
+ * nucleation, fraction s_soften of the GND densities a nucleus keeps. */
+typedef struct {
+  double kc, q, s_nucl, s_soften;
+} fftevp_drx;
+
+/* Enable DRX nucleation (Sec. 2.3, 2.5): draws the nucleation strength of
+ * every voxel by inverting the Weibull law P(kappa < k) = 1 - exp(-(k/kc)^q)
+ * (Eq. 9-10) at the caller's uniform numbers u_dev (device, FP64 [V], each
+ * in [0, 1), EINVAL otherwise; nothing is changed then). Needs GND tracking,
+ * whose grain ids define the grain-boundary sites (ESTATE otherwise).
+ * EINVAL unless kc, q, s_nucl > 0 and 0 <= s_soften <= 1. */
+fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double* u_dev);
+
+/* One nucleation test on the committed state (call after fftevp_step). A
+ * voxel with a face neighbour of another grain (periodic) nucleates when its
+ * total dislocation density (Eq. 12: per system, SSD + mobile + GND, the GND
+ * density being sqrt(screw^2 + edge^2); with the power law, which has one
+ * density and no mobile density, the voxel density + the GND densities)
+ * exceeds its strength. All sites are tested on the same state, then every
+ * nucleus becomes a single-voxel grain (id -(index + 1)), keeps s_soften of
+ * its GND densities (Eq. 16; SSD densities and orientation unchanged) and
+ * draws a new strength with s_nucl kc at u_dev (device, FP64 [V] in [0, 1),
+ * checked first: EINVAL changes nothing). The number of nuclei goes to
+ * *n_nuclei (may be NULL). With orientations inherited the elastic moduli do
+ * not change, so the stress needs no re-solve here. */
+fftevp_status fftevp_drx_nucleate(fftevp_ctx* ctx, const double* u_dev, long long* n_nuclei);
 
 /* One strain increment: the fixed-point solve, then the explicit update of
  * plastic strain and density at the converged stress (Eq. 1 first-order

@@ -39,6 +39,9 @@ struct Bufs {
   // the paper's law (allocated by set_law)
   void* ssd = nullptr;     // SSD density per system, [12][V]
   void* sysp = nullptr;    // tau_pass, 1/tau_cut, A per system, [3][12][V]
+  // DRX nucleation (allocated by set_drx)
+  void* kappa = nullptr;   // nucleation strength, [V]
+  int* grain2 = nullptr;   // second grain-id buffer, [V]
 };
 
 }  // namespace
@@ -68,6 +71,8 @@ struct fftevp_ctx {
   double E[6] = {0, 0, 0, 0, 0, 0};  // committed macroscopic strain (Mandel)
   bool gnd_on = false;
   int law = 0;          // 0: power law (hardening above), 1: the paper's law
+  bool drx_on = false;
+  fftevp_drx drx{};
   fftevp_mr mr{};
   MrConst mrc{};
   double leff = 0.0, xi = 0.0;  // effective length (m) and its constant
@@ -299,6 +304,8 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.gndet);
   f(ctx->b.ssd);
   f(ctx->b.sysp);
+  f(ctx->b.kappa);
+  f(ctx->b.grain2);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->b.a_eta);
   f(ctx->b.a_sigt);
@@ -593,7 +600,8 @@ size_t snap_layout(const fftevp_ctx* c, size_t off[8]) {
   if (c->gnd_on) o += 24 * V * ts;
   off[6] = o;  // SSD densities per system (paper's law), [12][V]
   if (c->law == 1) o += 12 * V * ts;
-  off[7] = o;
+  off[7] = o;  // DRX: nucleation strength [V] then grain ids [V] (int32)
+  if (c->drx_on) o += V * ts + ((V * sizeof(int) + 255) & ~(size_t)255);
   return o;
 }
 
@@ -860,6 +868,84 @@ fftevp_status fftevp_set_law(fftevp_ctx* ctx, int law, const fftevp_mr* p) {
   return mr_reset(ctx);
 }
 
+// uniforms in [0, 1): kappa = kc (-ln(1-u))^(1/q) into kappa (null: check only)
+static fftevp_status draw_kappa(fftevp_ctx* ctx, const double* u, void* kappa, double kc, double q) {
+  const size_t V = ctx->V;
+  HIPCHK(ctx->prec == FFTEVP_FP64
+             ? launch_kappa<double>(u, (double*)kappa, V, kc, q, ctx->partial, ctx->red_nb, ctx->red2, ctx->stream)
+             : launch_kappa<float>(u, (float*)kappa, V, kc, q, ctx->partial, ctx->red_nb, ctx->red2, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->red2_h[0] != 0.0) return fail(ctx, FFTEVP_EINVAL, "uniform numbers must lie in [0, 1)");
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double* u_dev) {
+  if (!ctx || !p || !u_dev) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (!(p->kc > 0 && std::isfinite(p->kc) && p->q > 0 && std::isfinite(p->q) && p->s_nucl > 0 &&
+        std::isfinite(p->s_nucl) && p->s_soften >= 0 && p->s_soften <= 1))
+    return fail(ctx, FFTEVP_EINVAL, "kc, q, s_nucl > 0 and 0 <= s_soften <= 1");
+  if (!ctx->gnd_on) return fail(ctx, FFTEVP_ESTATE, "DRX nucleation needs GND tracking (fftevp_set_gnd)");
+  const size_t V = ctx->V;
+  hipError_t e = hipSuccess;
+  void* kap = ctx->b.kappa;
+  if (!kap) e = hipMalloc(&kap, V * ctx->tsize);
+  if (e == hipSuccess && !ctx->b.grain2) e = hipMalloc((void**)&ctx->b.grain2, V * sizeof(int));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (kap && kap != ctx->b.kappa) (void)hipFree(kap);
+    return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
+  }
+  ctx->b.kappa = kap;
+  fftevp_status st = draw_kappa(ctx, u_dev, ctx->b.kappa, p->kc, p->q);
+  if (st != FFTEVP_OK) return st;
+  ctx->drx = *p;
+  ctx->drx_on = true;
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_drx_nucleate(fftevp_ctx* ctx, const double* u_dev, long long* n_nuclei) {
+  if (!ctx || !u_dev) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (!ctx->drx_on) return fail(ctx, FFTEVP_ESTATE, "DRX nucleation is not enabled (fftevp_set_drx)");
+  if (!ctx->state_ok)
+    return fail(ctx, FFTEVP_ESTATE, "an adjoint solve reused the state buffers: load a snapshot first");
+  fftevp_status st = draw_kappa(ctx, u_dev, nullptr, 1.0, 1.0);
+  if (st != FFTEVP_OK) return st;
+  auto run = [&](auto tag) -> hipError_t {
+    using T = decltype(tag);
+    DrxArgs<T> a{};
+    a.grain = ctx->b.grain;
+    a.grain_out = ctx->b.grain2;
+    a.gs = (T*)ctx->b.gnds;
+    a.ge = (T*)ctx->b.gndet;
+    a.ssd = (const T*)ctx->b.ssd;
+    a.rho = (const T*)ctx->b.rho;
+    a.kappa = (T*)ctx->b.kappa;
+    a.u = u_dev;
+    a.partial = ctx->partial;
+    a.V = ctx->V;
+    a.n0 = ctx->n0;
+    a.n1 = ctx->n1;
+    a.n2 = ctx->n2;
+    a.rhom_c = ctx->mrc.rhom_c;
+    a.s_soften = ctx->drx.s_soften;
+    a.kc_new = ctx->drx.s_nucl * ctx->drx.kc;
+    a.iq = 1.0 / ctx->drx.q;
+    return launch_drx<T>(a, ctx->law == 1, ctx->red_nb, ctx->red2, ctx->stream);
+  };
+  HIPCHK(ctx->prec == FFTEVP_FP64 ? run(double{}) : run(float{}));
+  HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::swap(ctx->b.grain, ctx->b.grain2);
+  if (n_nuclei) *n_nuclei = (long long)ctx->red2_h[0];
+  // the paper's law: GND densities changed, so do the next parameters
+  if (ctx->law == 1) {
+    HIPCHK(mr_params(ctx));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  return FFTEVP_OK;
+}
+
 fftevp_status fftevp_set_gnd(fftevp_ctx* ctx, const int* grain_dev, double l0, double xi) {
   if (!ctx || !grain_dev) return fail(ctx, FFTEVP_EINVAL, "null argument");
   if (!(l0 > 0.0 && std::isfinite(l0) && xi > 0.0 && std::isfinite(xi)))
@@ -952,6 +1038,14 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
     case FFTEVP_FIELD_RHO: e = exp(ctx->b.rho, 1, 0); break;
     case FFTEVP_FIELD_SIGMA_ITER: e = exp(ctx->b.sig[ctx->sw], 6, 1); break;
     case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->e_last); break;
+    case FFTEVP_FIELD_KAPPA:
+      if (!ctx->drx_on) return fail(ctx, FFTEVP_ESTATE, "DRX nucleation is not enabled (fftevp_set_drx)");
+      e = exp(ctx->b.kappa, 1, 0);
+      break;
+    case FFTEVP_FIELD_GRAIN:
+      if (!ctx->gnd_on) return fail(ctx, FFTEVP_ESTATE, "grain ids come with fftevp_set_gnd");
+      e = launch_export_int(ctx->b.grain, dst, V, ctx->stream);
+      break;
     case FFTEVP_FIELD_RHO_SSD:
       if (ctx->law != 1) return fail(ctx, FFTEVP_ESTATE, "per-system SSD densities need the paper's law");
       e = exp(ctx->b.ssd, 12, 0);
@@ -1016,6 +1110,7 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   hdr[14] = ctx->gnd_on ? 1.0 : 0.0;
   hdr[15] = ctx->leff;
   hdr[16] = ctx->law;
+  hdr[17] = ctx->drx_on ? 1.0 : 0.0;
   char* d = (char*)dst;
   HIPCHK(hipMemcpyAsync(d, hdr, sizeof hdr, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(d + off[0], ctx->b.epsp, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1031,6 +1126,10 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   }
   if (ctx->law == 1)
     HIPCHK(hipMemcpyAsync(d + off[6], ctx->b.ssd, 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->drx_on) {
+    HIPCHK(hipMemcpyAsync(d + off[7], ctx->b.kappa, V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d + off[7] + V * ts, ctx->b.grain, V * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FFTEVP_OK;
 }
@@ -1045,7 +1144,8 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   HIPCHK(hipMemcpyAsync(hdr, s, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
-      hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0) || hdr[16] != (double)ctx->law)
+      hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0) || hdr[16] != (double)ctx->law ||
+      hdr[17] != (ctx->drx_on ? 1.0 : 0.0))
     return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
   HIPCHK(hipMemcpyAsync(ctx->b.epsp, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.rho, s + off[1], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1058,6 +1158,10 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
     HIPCHK(hipMemcpyAsync(ctx->b.gndet, s + off[5] + 12 * V * ts, 12 * V * ts, hipMemcpyDeviceToDevice,
                           ctx->stream));
     ctx->leff = hdr[15];
+  }
+  if (ctx->drx_on) {
+    HIPCHK(hipMemcpyAsync(ctx->b.kappa, s + off[7], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->b.grain, s + off[7] + V * ts, V * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
   }
   if (ctx->law == 1) {
     HIPCHK(hipMemcpyAsync(ctx->b.ssd, s + off[6], 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));

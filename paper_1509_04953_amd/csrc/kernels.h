@@ -123,6 +123,23 @@ struct MrConst {
   double rhom_c, dd_c, climb_c;
 };
 
+// DRX nucleation test (Sec. 2.3, 2.5)
+template <typename T>
+struct DrxArgs {
+  const int* grain;   // [V] in
+  int* grain_out;     // [V] out
+  T* gs;              // screw GND densities [12][V] (in/out)
+  T* ge;              // edge GND densities [12][V] (in/out)
+  const T* ssd;       // paper's law: per-system SSD [12][V]
+  const T* rho;       // power law: voxel density [V]
+  T* kappa;           // nucleation strength [V] (in/out)
+  const double* u;    // uniforms for the redraws [V]
+  double* partial;    // [blocks][2]: nuclei count
+  size_t V;
+  int n0, n1, n2;
+  double rhom_c, s_soften, kc_new, iq;
+};
+
 template <typename T>
 struct StateArgs {
   const T* sig;
@@ -189,6 +206,12 @@ template <typename T>
 hipError_t launch_state_mr(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
 template <typename T>
 hipError_t launch_split12(const T* rho, T* ssd, size_t V, hipStream_t s);
+template <typename T>
+hipError_t launch_kappa(const double* u, T* kappa, size_t V, double kc, double q, double* partial, int nblocks,
+                        double* out2, hipStream_t s);
+template <typename T>
+hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, hipStream_t s);
+hipError_t launch_export_int(const int* src, double* dst, size_t V, hipStream_t s);
 template <typename T>
 hipError_t launch_mr_params(const T* ssd, const T* gnds, const T* gndet, T* sysp, size_t V, const MrConst& c,
                             hipStream_t s);

@@ -1079,6 +1079,85 @@ __global__ __launch_bounds__(256) void k_gdot_mr(const T* __restrict__ sig, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// DRX nucleation (Sec. 2.3, 2.5)
+// ---------------------------------------------------------------------------
+// nucleation strength kappa = kc (-ln(1 - u))^(1/q) (inverse of the Weibull
+// law of Eq. 9-10); counts the uniforms outside [0, 1)
+template <typename T>
+__global__ __launch_bounds__(256) void k_kappa(const double* __restrict__ u, T* __restrict__ kappa, size_t V,
+                                               double kc, double iq, double* partial) {
+  double bad[2] = {0.0, 0.0};
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    const double x = u[g];
+    if (!(x >= 0.0 && x < 1.0)) {
+      bad[0] += 1.0;
+      continue;
+    }
+    if (kappa) kappa[g] = (T)(kc * pow(-log1p(-x), iq));
+  }
+  block_reduce<2, 0>(bad, partial + (size_t)blockIdx.x * 2);
+}
+
+// One nucleation test on the state after an increment: a voxel with a face
+// neighbour of another grain nucleates when its total dislocation density
+// (Eq. 12: per-system SSD + GND (sqrt of screw^2 + edge^2) + mobile for the
+// paper's law; the voxel density + GND for the power law) exceeds its
+// strength. A nucleus becomes a single-voxel grain (id -(index + 1)), keeps
+// s_soften of its GND densities (Eq. 16) and draws a new strength with
+// s_nucl kc. Grain ids are read from one buffer and written to another.
+template <typename T, bool MRLAW>
+__global__ __launch_bounds__(256) void k_drx(DrxArgs<T> a) {
+  const size_t V = a.V;
+  double cnt[2] = {0.0, 0.0};
+  const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    const int x = (int)(g % n0), y = (int)((g / n0) % n1), z = (int)(g / ((size_t)n0 * n1));
+    const size_t sy = (size_t)n0, sz = (size_t)n0 * n1;
+    const int me = a.grain[g];
+    const size_t nb[6] = {x + 1 < n0 ? g + 1 : g + 1 - n0, x > 0 ? g - 1 : g - 1 + n0,
+                          y + 1 < n1 ? g + sy : g + sy - (size_t)n1 * sy, y > 0 ? g - sy : g - sy + (size_t)n1 * sy,
+                          z + 1 < n2 ? g + sz : g + sz - (size_t)n2 * sz, z > 0 ? g - sz : g - sz + (size_t)n2 * sz};
+    bool site = false;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) site |= a.grain[nb[k]] != me;
+    int out = me;
+    if (site) {
+      double k = 0.0;
+#pragma unroll
+      for (int al = 0; al < 12; ++al) {
+        const double gs = a.gs[(size_t)al * V + g], ge = a.ge[(size_t)al * V + g];
+        k += sqrt(gs * gs + ge * ge);
+      }
+      if constexpr (MRLAW) {
+        double F[12], P[12];
+        mr_projections(a.ssd, a.gs, a.ge, V, g, F, P);
+#pragma unroll
+        for (int al = 0; al < 12; ++al) k += (double)a.ssd[(size_t)al * V + g] + a.rhom_c * sqrt(P[al] * F[al]);
+      } else {
+        k += (double)a.rho[g];
+      }
+      if (k > (double)a.kappa[g]) {
+        out = -(int)(g + 1);
+        cnt[0] += 1.0;
+#pragma unroll
+        for (int al = 0; al < 12; ++al) {
+          a.gs[(size_t)al * V + g] = (T)(a.s_soften * (double)a.gs[(size_t)al * V + g]);
+          a.ge[(size_t)al * V + g] = (T)(a.s_soften * (double)a.ge[(size_t)al * V + g]);
+        }
+        a.kappa[g] = (T)(a.kc_new * pow(-log1p(-a.u[g]), a.iq));
+      }
+    }
+    a.grain_out[g] = out;
+  }
+  block_reduce<2, 0>(cnt, a.partial + (size_t)blockIdx.x * 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_export_int(const int* __restrict__ src, double* __restrict__ dst, size_t V) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) dst[g] = src[g];
+}
+
 __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ p, int n, double* out) {
   double v[2] = {0.0, 0.0};
   for (int b = threadIdx.x; b < n; b += 256) {
@@ -1430,6 +1509,27 @@ hipError_t launch_gdot_mr(const T* sig, const T* quat, const T* sysp, double* ou
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_kappa(const double* u, T* kappa, size_t V, double kc, double q, double* partial, int nblocks,
+                        double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_kappa<T>, dim3(nblocks), dim3(256), 0, s, u, kappa, V, kc, 1.0 / q, partial);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, (const double*)partial, nblocks, out2);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, hipStream_t s) {
+  if (mr) hipLaunchKernelGGL((k_drx<T, true>), dim3(nblocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_drx<T, false>), dim3(nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, (const double*)a.partial, nblocks, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_int(const int* src, double* dst, size_t V, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_int<double>, dim3(grid_for(V)), dim3(256), 0, s, src, dst, V);
+  return hipGetLastError();
+}
+
 // GND update of one increment from the slip rates k_state left in gd.
 template <typename T>
 hipError_t launch_gnd(const GndArgs<T>& a, hipStream_t s) {
@@ -1481,6 +1581,9 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_gnd<T>(const GndArgs<T>&, hipStream_t);                          \
   template hipError_t launch_state_mr<T>(const StateArgs<T>&, int, double*, hipStream_t);      \
   template hipError_t launch_split12<T>(const T*, T*, size_t, hipStream_t);                   \
+  template hipError_t launch_kappa<T>(const double*, T*, size_t, double, double, double*, int, double*, \
+                                      hipStream_t);                                           \
+  template hipError_t launch_drx<T>(const DrxArgs<T>&, bool, int, double*, hipStream_t);      \
   template hipError_t launch_mr_params<T>(const T*, const T*, const T*, T*, size_t, const MrConst&, \
                                           hipStream_t);                                       \
   template hipError_t launch_gdot_mr<T>(const T*, const T*, const T*, double*, size_t, hipStream_t); \

@@ -19,11 +19,11 @@ _lib = None
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENONFINITE, ELOCAL, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5, "gdot": 6,
-          "rho_gnds": 7, "rho_gndet": 8, "rho_ssd": 9}
+          "rho_gnds": 7, "rho_gndet": 8, "rho_ssd": 9, "kappa": 10, "grain": 11}
 NPROF = 8
 PROF_NAMES = ("local", "unused", "yfwd", "zgamma", "yinv", "state", "adjoint", "gnd")
 NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6, "gdot": 12,
-         "rho_gnds": 12, "rho_gndet": 12, "rho_ssd": 12}
+         "rho_gnds": 12, "rho_gndet": 12, "rho_ssd": 12, "kappa": 1, "grain": 1}
 
 
 class Cubic(C.Structure):
@@ -33,6 +33,10 @@ class Cubic(C.Structure):
 class MRC(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("T", "Q_slip", "Q_bulk", "c1", "c2", "c3", "c4", "c5", "c6",
                                           "c7", "c8", "nu_D", "poisson")]
+
+
+class DrxC(C.Structure):
+    _fields_ = [("kc", C.c_double), ("q", C.c_double), ("s_nucl", C.c_double), ("s_soften", C.c_double)]
 
 
 class FlowC(C.Structure):
@@ -73,6 +77,8 @@ def library():
         "fftevp_set_loading": (I, [P, C.POINTER(LoadingC)]),
         "fftevp_set_gnd": (I, [P, P, C.c_double, C.c_double]),
         "fftevp_set_law": (I, [P, I, C.POINTER(MRC)]),
+        "fftevp_set_drx": (I, [P, C.POINTER(DrxC), P]),
+        "fftevp_drx_nucleate": (I, [P, P, C.POINTER(C.c_longlong)]),
         "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_get_field": (I, [P, I, P]),
         "fftevp_state_bytes": (S, [P]),
@@ -233,6 +239,19 @@ class Solver:
             return
         c = MRC(*(getattr(law, k) for k, _ in MRC._fields_))
         self._check(self.lib.fftevp_set_law(self.h, 1, C.byref(c)))
+
+    def set_drx(self, u, kc: float = 300e12, q: float = 4.4, s_nucl: float = 0.05, s_soften: float = 0.9):
+        """DRX nucleation strengths from uniforms ``u`` (one per voxel, [0, 1))."""
+        t = self._dev(u, (self.nvox,))
+        self._check(self.lib.fftevp_set_drx(self.h, C.byref(DrxC(kc, q, s_nucl, s_soften)),
+                                            C.c_void_p(t.data_ptr())))
+
+    def drx_nucleate(self, u) -> int:
+        """One nucleation test; ``u``: fresh uniforms for the redraws."""
+        t = self._dev(u, (self.nvox,))
+        n = C.c_longlong(0)
+        self._check(self.lib.fftevp_drx_nucleate(self.h, C.c_void_p(t.data_ptr()), C.byref(n)))
+        return int(n.value)
 
     def set_gnd(self, grains, l0: float = 21.4e-6, xi: float = 200.0):
         """Track GND densities (screw and edge, per slip system) from every
