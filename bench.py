@@ -190,6 +190,33 @@ def run_mr(w, quat, rho, precision, steps=3, warmup=1):
             "local_frac_hbm": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def run_drx(w, quat, rho, grains, precision, tests=4):
+    """DRX nucleation test (Sec. 2.3, 2.5) on the same workload after one
+    increment with GND tracking: wall time per test with the uniforms
+    already on the device (validation pass + nucleation kernel + count)."""
+    import torch
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load(dt=w.dt))
+    s.set_gnd(grains.reshape(-1))
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    u = torch.rand(w.voxels, dtype=torch.float64, device="cuda", generator=gen)
+    s.set_drx(u, kc=2.0e12)
+    s.step(Opts(tol=w.tol, max_iter=2000))
+    us = [torch.rand(w.voxels, dtype=torch.float64, device="cuda", generator=gen) for _ in range(tests)]
+    torch.cuda.synchronize()
+    n = []
+    t0 = time.perf_counter()
+    for u in us:
+        n.append(s.drx_nucleate(u))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / tests
+    s.close()
+    return {"precision": precision, "ms_per_test": dt * 1e3, "nuclei": n}
+
+
 def source_hash():
     """Prefix of the sha256 of the device sources (matches the profiles)."""
     import hashlib
@@ -383,6 +410,8 @@ def main():
                                                        / np.max(np.abs(r["s33"])))}
     if not args.no_gnd:
         line["gnd"] = run_gnd(w, quat, rho, grains, precs[0])
+    if not args.no_gnd:
+        line["drx"] = run_drx(w, quat, rho, grains, precs[0])
     if not args.no_mr:
         line["paper_law"] = {p: run_mr(w, quat, rho, p) for p in precs}
     if not args.no_adjoint:
