@@ -217,7 +217,7 @@ fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double*
 
 /* One nucleation test on the committed state (call after fftevp_step). A
  * voxel with a face neighbour of another grain (periodic) nucleates when its
- * total dislocation density (Eq. 12: per system, SSD + mobile + GND, the GND
+ * total dislocation density (Eq. 11: per system, SSD + mobile + GND, the GND
  * density being sqrt(screw^2 + edge^2); with the power law, which has one
  * density and no mobile density, the voxel density + the GND densities)
  * exceeds its strength. All sites are tested on the same state, then every

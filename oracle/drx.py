@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.
 * Nucleation strength: kappa(x) follows the Weibull law of Eq. 9-10,
   P(kappa < k) = 1 - exp(-(k/k_c)^q); drawn by inverting that distribution
   at caller-supplied uniform numbers u in (0, 1): kappa = k_c (-ln(1-u))^(1/q).
-* Propensity: k(x) = rho_tot(x) (Eq. 12), the sum over systems of mobile, SSD
+* Propensity: k(x) = rho_tot(x) (Eq. 11), the sum over systems of mobile, SSD
   and GND densities. Readings: the GND density of a system is
   sqrt(rho_GNDs^2 + rho_GNDet^2) (the conservation law stated with Eq. 7,
   rho_GNDen = 0); with the power law, which has one density per voxel and no
@@ -57,7 +57,7 @@ def gb_sites(grains, shape):
 
 
 def total_density(rho, rho_gs, rho_get, law=None, rho_ssd=None):
-    """k(x) = rho_tot (Eq. 12). rho: (V,) voxel density; rho_gs, rho_get:
+    """k(x) = rho_tot (Eq. 11). rho: (V,) voxel density; rho_gs, rho_get:
     (12, V) GND densities or None; law: MaRoters with rho_ssd (V, 12) for the
     paper's law (adds the mobile densities)."""
     gnd = 0.0 if rho_gs is None else np.sqrt(rho_gs ** 2 + rho_get ** 2).sum(axis=0)

@@ -1,10 +1,10 @@
-"""Phase-field growth of recrystallised grains (Sec. 2.4, Eq. 13-15) —
+"""Phase-field growth of recrystallised grains (Sec. 2.4, Eq. 12-15) —
 TEST INFRASTRUCTURE ONLY.
 
 Two order parameters per grain, eta_rex,i and eta_def,i (a deformed grain
 has eta_def = 1, a recrystallised one eta_rex = 1). Free energy density:
-the multi-well grain-boundary term of Eq. 14 with its gradient energy, and
-the stored energy of Eq. 15, f_def = E_store D / S with D = sum eta_def^2,
+the multi-well grain-boundary term of Eq. 13 with its gradient energy, and
+the stored energy of Eq. 14, f_def = E_store D / S with D = sum eta_def^2,
 S = sum (eta_rex^2 + eta_def^2), E_store = rho_tot zeta mu b^2. Allen-Cahn
 (Eq. 15) for every order parameter eta_p:
 
@@ -14,9 +14,13 @@ S = sum (eta_rex^2 + eta_def^2), E_store = rho_tot zeta mu b^2. Allen-Cahn
     d f_def / d eta_def,i =  2 E_store eta_def,i R / S^2,  R = sum eta_rex^2,
 
 with m = 6 omega/l, kappa = 3 omega l / 4, L = 4 M / (3 l) (the coefficients
-of Eq. 14-15).
+of Eq. 13 and 15).
 
-Readings. Units: the paper fixes the discretisation by 6 omega = l (in the
+Readings. Pair coefficient: as printed, Eq. 13 counts every (rex, def)
+pair twice (once in each line) and every (rex, rex) or (def, def) pair once;
+the coefficient relations it takes from the quantitative model hold for the
+symmetric multi-well form with the same pair coefficient 3/2 on every pair,
+which is the form used here (the derivative above). Units: the paper fixes the discretisation by 6 omega = l (in the
 units of the quantitative scheme it cites), l = sqrt(9.6) dx and
 M dt = 0.0375 l; the solver works in those units, grid spacing dx = 1 and
 one PF step dt = 1, so l = sqrt(9.6), omega = l/6, M = 0.0375 l, i.e.
@@ -31,7 +35,7 @@ point (2i + a) (a in {0, 1} per axis) takes the grain of coarse point i
 (nearest grid point; the midpoints take the lower one) and E_store from
 trilinear interpolation of the coarse points i and i + 1 (periodic); after
 the PF steps coarse point i takes the grain of the largest order parameter
-at fine point 2i. Order parameter keys: 2 id + kind (kind 1 = rex, 0 = def);
+at fine point 2i (reading: a point that holds none keeps its grain). Order parameter keys: 2 id + kind (kind 1 = rex, 0 = def);
 nuclei (negative ids) start recrystallised.
 
 Arrays: dense order parameters (P, Vf) over an explicit key list; voxels
@@ -139,9 +143,10 @@ def initial_state(grains_c, shape_c):
     return keys, eta
 
 
-def coarse_grains(keys, eta, shape_c):
-    """Grain of the largest order parameter at fine point 2i, per coarse i."""
+def coarse_grains(keys, eta, shape_c, grains_before):
+    """Grain of the largest order parameter at fine point 2i, per coarse i
+    (equal values: the smaller key); a point holding none keeps its grain."""
     n0, n1, n2 = shape_c
     e = eta.reshape(len(keys), 2 * n2, 2 * n1, 2 * n0)[:, ::2, ::2, ::2].reshape(len(keys), -1)
     k = keys[np.argmax(e, axis=0)]
-    return np.floor_divide(k, 2)
+    return np.where(e.max(axis=0) > 0, np.floor_divide(k, 2), np.asarray(grains_before).reshape(-1))

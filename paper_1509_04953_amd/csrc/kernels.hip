@@ -1101,7 +1101,7 @@ __global__ __launch_bounds__(256) void k_kappa(const double* __restrict__ u, T* 
 
 // One nucleation test on the state after an increment: a voxel with a face
 // neighbour of another grain nucleates when its total dislocation density
-// (Eq. 12: per-system SSD + GND (sqrt of screw^2 + edge^2) + mobile for the
+// (Eq. 11: per-system SSD + GND (sqrt of screw^2 + edge^2) + mobile for the
 // paper's law; the voxel density + GND for the power law) exceeds its
 // strength. A nucleus becomes a single-voxel grain (id -(index + 1)), keeps
 // s_soften of its GND densities (Eq. 16) and draws a new strength with

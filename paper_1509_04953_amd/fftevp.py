@@ -90,6 +90,14 @@ def library():
         "fftevp_get_profile": (I, [P, D, C.POINTER(C.c_longlong), I]),
         "fftevp_status_string": (C.c_char_p, [I]),
         "fftevp_last_error": (C.c_char_p, [P]),
+        "fftevp_pf_create": (I, [I, I, I, I, C.c_double, I, P, C.POINTER(P)]),
+        "fftevp_pf_destroy": (I, [P]),
+        "fftevp_pf_refine": (I, [P, P, P]),
+        "fftevp_pf_import": (I, [P, P, P, I, P]),
+        "fftevp_pf_steps": (I, [P, I]),
+        "fftevp_pf_export": (I, [P, P, P]),
+        "fftevp_pf_grains": (I, [P, P, P]),
+        "fftevp_pf_last_error": (C.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -322,3 +330,81 @@ class Solver:
             self.h, C.byref(_opts(opts)), C.c_void_p(before.data_ptr()), C.c_void_p(after.data_ptr()),
             g, C.c_void_p(adj.data_ptr()), th))
         return np.array(th[:])
+
+
+class PhaseField:
+    """Phase-field growth of recrystallised grains (include/fftevp_pf.h) on
+    the grid that refines an ``shape`` (n0, n1, n2) mechanical grid 2:1."""
+
+    def __init__(self, shape, K: int = 6, threshold: float = 1e-5, precision: str = "fp64", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("fftevp needs a GPU; no CPU fallback exists")
+        self.torch = torch
+        self.lib = library()
+        self.shape = tuple(int(s) for s in shape)
+        self.nvox = int(np.prod(self.shape))
+        self.nfine = 8 * self.nvox
+        self.K = int(K)
+        self.stream = stream or torch.cuda.current_stream()
+        prec = {"fp64": FP64, "mixed": MIXED}[precision]
+        h = C.c_void_p()
+        st = self.lib.fftevp_pf_create(*self.shape, self.K, float(threshold), prec,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise FftevpError(st, self.lib.fftevp_status_string(st).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fftevp_pf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise FftevpError(st, self.lib.fftevp_pf_last_error(self.h).decode())
+
+    def _t(self, a, dtype, n):
+        t = self.torch.as_tensor(np.asarray(a) if not self.torch.is_tensor(a) else a, dtype=dtype,
+                                 device="cuda").reshape(-1).contiguous()
+        if t.numel() != n:
+            raise ValueError(f"expected {n} values, got {t.numel()}")
+        return t
+
+    def refine(self, grains, estore):
+        """Sharp start from a grain map and stored energy on the mechanical grid."""
+        g = self._t(grains, self.torch.int32, self.nvox)
+        e = self._t(estore, self.torch.float64, self.nvox)
+        self._check(self.lib.fftevp_pf_refine(self.h, C.c_void_p(g.data_ptr()), C.c_void_p(e.data_ptr())))
+
+    def load(self, keys, vals, estore):
+        """State from slot-major (kin, Vf) keys and values and a fine stored energy."""
+        kin = int(np.shape(keys)[0])
+        k = self._t(keys, self.torch.int32, kin * self.nfine)
+        v = self._t(vals, self.torch.float64, kin * self.nfine)
+        e = self._t(estore, self.torch.float64, self.nfine)
+        self._check(self.lib.fftevp_pf_import(self.h, C.c_void_p(k.data_ptr()), C.c_void_p(v.data_ptr()),
+                                              kin, C.c_void_p(e.data_ptr())))
+
+    def steps(self, n: int):
+        self._check(self.lib.fftevp_pf_steps(self.h, int(n)))
+
+    def state(self):
+        """(keys int32 (K, Vf), values float64 (K, Vf)) on the device."""
+        k = self.torch.empty((self.K, self.nfine), dtype=self.torch.int32, device="cuda")
+        v = self.torch.empty((self.K, self.nfine), dtype=self.torch.float64, device="cuda")
+        self._check(self.lib.fftevp_pf_export(self.h, C.c_void_p(k.data_ptr()), C.c_void_p(v.data_ptr())))
+        return k, v
+
+    def grains(self, before):
+        """Grain map on the mechanical grid read from the state."""
+        b = self._t(before, self.torch.int32, self.nvox)
+        out = self.torch.empty_like(b)
+        self._check(self.lib.fftevp_pf_grains(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out

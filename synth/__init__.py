@@ -27,7 +27,7 @@ from scipy.spatial import cKDTree
 __all__ = [
     "Workload", "WORKLOADS", "workload", "voronoi_grains", "random_quaternions",
     "lognormal_rho", "grain_boundary_nuclei", "make_microstructure",
-    "random_voxel_states",
+    "random_voxel_states", "single_voxel_nuclei",
 ]
 
 
@@ -161,6 +161,21 @@ def grain_boundary_nuclei(grains: np.ndarray, rho: np.ndarray, fraction: float,
         count += int(new.sum())
     out[covered] = rho_nuc
     return out
+
+
+def single_voxel_nuclei(grains: np.ndarray, fraction: float, rng) -> np.ndarray:
+    """Grain map with DRX-like nuclei: a random ``fraction`` of the
+    grain-boundary voxels (periodic face neighbour in another grain) become
+    one-voxel grains with id ``-(flat index + 1)``."""
+    gb = np.zeros(grains.shape, dtype=bool)
+    for ax in range(3):
+        for s in (1, -1):
+            gb |= grains != np.roll(grains, s, axis=ax)
+    idx = np.flatnonzero(gb)
+    pick = idx[rng.random(idx.size) < fraction]
+    out = grains.copy().reshape(-1)
+    out[pick] = -(pick + 1)
+    return out.reshape(grains.shape)
 
 
 def make_microstructure(w: Workload):

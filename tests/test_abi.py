@@ -7,7 +7,7 @@ from pathlib import Path
 import pytest
 
 ROOT = Path(__file__).resolve().parents[1]
-HEADER = ROOT / "include" / "fftevp.h"
+HEADERS = sorted((ROOT / "include").glob("*.h"))
 LIB = ROOT / "paper_1509_04953_amd" / "libfftevp.so"
 
 
@@ -20,13 +20,13 @@ def lib():
 
 
 def declared():
-    text = HEADER.read_text()
+    text = "".join(h.read_text() for h in HEADERS)
     return sorted(set(re.findall(r"\b(fftevp_[a-z_]+)\s*\(", text)))
 
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared()
-    assert len(names) >= 16
+    assert len(names) >= 24 and "fftevp_pf_steps" in names
     for n in names:
         assert hasattr(lib, n), n
 
@@ -59,3 +59,22 @@ def test_null_context_calls(lib):
     assert lib.fftevp_state_bytes(None) == 0
     assert lib.fftevp_set_profiling(None, 1) == -1
     assert lib.fftevp_last_error(None) == b"null context"
+
+
+@pytest.mark.parametrize("args", [(0, 4, 4, 6, 1e-5, 0), (4, 4, 4, 0, 1e-5, 0), (4, 4, 4, 7, 1e-5, 0),
+                                  (4, 4, 4, 6, -1.0, 0), (4, 4, 4, 6, 1.0, 0), (4, 4, 4, 6, 1e-5, 3),
+                                  (1024, 1024, 512, 6, 1e-5, 0)])
+def test_pf_create_rejects_bad_arguments(lib, args):
+    h = C.c_void_p()
+    assert lib.fftevp_pf_create(*args, None, C.byref(h)) == -1
+    assert not h.value
+
+
+def test_pf_null_context_calls(lib):
+    assert lib.fftevp_pf_destroy(None) == -1
+    assert lib.fftevp_pf_steps(None, 1) == -1
+    assert lib.fftevp_pf_refine(None, None, None) == -1
+    assert lib.fftevp_pf_export(None, None, None) == -1
+    assert lib.fftevp_pf_grains(None, None, None) == -1
+    assert lib.fftevp_pf_import(None, None, None, 1, None) == -1
+    assert lib.fftevp_pf_last_error(None) == b"null context"

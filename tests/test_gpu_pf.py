@@ -1,0 +1,221 @@
+"""Phase-field growth (Sec. 2.4, Eq. 12-15) on the GPU against the oracle
+through the C ABI: the 2:1 refinement, the sparse explicit steps with
+truncation (FP64 and FP32), the grain map read back, input checks and a
+full-size run compared point by point on sampled windows."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pf as OPF
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12   # absolute, order parameters are O(1); a few roundings per step
+TOL32 = 3e-5    # absolute after 30 FP32 steps
+
+
+def inputs(shape, n_grains, seed, e_median=0.5, nuclei=0.2):
+    """Grain map (with one-voxel nuclei) and stored energy (solver units)."""
+    g = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3)]
+    grains = synth.voronoi_grains(shape, n_grains, g[0])
+    grains = synth.single_voxel_nuclei(grains, nuclei, g[1]).reshape(-1)
+    E = synth.lognormal_rho(shape, e_median, 0.3, g[2]).reshape(-1)
+    return grains, E
+
+
+def dense(pf, keys):
+    """GPU state as dense (P, Vf) over the oracle's key list (asserting that
+    the GPU holds no other key)."""
+    k, v = (t.cpu().numpy() for t in pf.state())
+    Vf = k.shape[1]
+    out = np.zeros((len(keys), Vf))
+    used = v > 0
+    pos = np.searchsorted(keys, k[used])
+    assert np.all(pos < len(keys)) and np.array_equal(keys[np.minimum(pos, len(keys) - 1)], k[used])
+    cols = np.nonzero(used)[1]
+    out[pos, cols] = v[used]
+    return out, k, v
+
+
+def oracle_run(grains, E, shape, steps, K, thr):
+    keys, eta = OPF.initial_state(grains, shape)
+    Ef = OPF.refine_linear(E, shape)
+    is_rex = (keys & 1) == 1
+    pf = OPF.PF(K=K, threshold=thr)
+    fine = tuple(2 * s for s in shape)
+    for _ in range(steps):
+        eta = OPF.pf_step(eta, is_rex, Ef, fine, pf)
+    return keys, eta
+
+
+def test_refine_is_the_oracles(require_gpu):
+    from paper_1509_04953_amd import PhaseField
+    shape = (5, 6, 7)
+    grains, E = inputs(shape, 6, 301)
+    pf = PhaseField(shape, K=6)
+    pf.refine(grains, E)
+    keys, eta = OPF.initial_state(grains, shape)
+    d, k, v = dense(pf, keys)
+    assert np.array_equal(d, eta)
+    assert np.all(k[1:] == np.iinfo(np.int32).min) and np.all(v[1:] == 0)
+    assert np.array_equal(pf.grains(grains).cpu().numpy(), grains)
+    pf.close()
+
+
+@pytest.mark.parametrize("shape,steps", [((5, 6, 7), 40), ((8, 8, 8), 60), ((1, 1, 1), 5), ((3, 1, 2), 12)])
+def test_steps_match_oracle_fp64(require_gpu, shape, steps):
+    from paper_1509_04953_amd import PhaseField
+    grains, E = inputs(shape, 6, 302 + steps)
+    pf = PhaseField(shape, K=6, threshold=1e-5)
+    pf.refine(grains, E)
+    pf.steps(steps)
+    keys, eta = oracle_run(grains, E, shape, steps, 6, 1e-5)
+    d, k, v = dense(pf, keys)
+    err = np.abs(d - eta).max()
+    print(f"pf fp64 {shape} {steps} steps: max |diff| {err:.2e}, points {d.shape[1]}, keys {len(keys)}")
+    assert err < TOL64, err
+    assert np.array_equal(d > 0, eta > 0)
+    # slots in decreasing value, then increasing key
+    for j in range(k.shape[0] - 1):
+        a, b = v[j], v[j + 1]
+        assert np.all((a > b) | ((a == b) & ((k[j] < k[j + 1]) | (b == 0))))
+    assert np.array_equal(pf.grains(grains).cpu().numpy(), OPF.coarse_grains(keys, eta, shape, grains))
+    pf.close()
+
+
+def test_steps_match_oracle_fp32(require_gpu):
+    from paper_1509_04953_amd import PhaseField
+    shape = (6, 5, 7)
+    grains, E = inputs(shape, 5, 310)
+    pf = PhaseField(shape, K=6, threshold=1e-5, precision="mixed")
+    pf.refine(grains, E)
+    pf.steps(30)
+    keys, eta = oracle_run(grains, E, shape, 30, 6, 1e-5)
+    d, _, _ = dense(pf, keys)
+    err = np.abs(d - eta).max()
+    print(f"pf fp32 {shape} 30 steps: max |diff| {err:.2e}")
+    assert err < TOL32, err
+    pf.close()
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_truncation_to_K_matches_oracle(require_gpu, K):
+    """Random states with more keys per point than K: the import keeps the K
+    largest, every step truncates again."""
+    from paper_1509_04953_amd import PhaseField
+    shape = (4, 3, 5)
+    fine = (8, 6, 10)
+    Vf = 8 * 60
+    rng = np.random.default_rng(320 + K)
+    P = 5
+    keys = np.array([-7, -2, 4, 9, 12], dtype=np.int32)      # rex: -7, 9; def: -2, 4, 12
+    eta = rng.random((P, Vf)) * (rng.random((P, Vf)) < 0.6)
+    Ef = rng.random(Vf)
+    pf = PhaseField(shape, K=K, threshold=1e-5)
+    kin = np.repeat(keys[:, None], Vf, axis=1)
+    pf.load(kin, eta, Ef)
+    o = OPF.truncate(eta, K, 1e-5)
+    d, _, _ = dense(pf, keys)
+    assert np.array_equal(d, o)
+    is_rex = (keys & 1) == 1
+    cfg = OPF.PF(K=K, threshold=1e-5)
+    for _ in range(8):
+        o = OPF.pf_step(o, is_rex, Ef, fine, cfg)
+    pf.steps(8)
+    d, _, _ = dense(pf, keys)
+    err = np.abs(d - o).max()
+    assert err < TOL64, err
+    assert np.array_equal(d > 0, o > 0)
+    pf.close()
+
+
+def test_zero_steps_and_input_checks(require_gpu):
+    import torch
+    from paper_1509_04953_amd import PhaseField, FftevpError, EINVAL, ESTATE
+    shape = (2, 2, 2)
+    Vf = 64
+    pf = PhaseField(shape, K=2)
+    with pytest.raises(FftevpError) as e:
+        pf.steps(1)
+    assert e.value.status == ESTATE
+    keys = np.array([[3] * Vf, [3] * Vf], dtype=np.int32)
+    vals = np.full((2, Vf), 0.5)
+    with pytest.raises(FftevpError) as e:       # key 3 twice at every point
+        pf.load(keys, vals, np.zeros(Vf))
+    assert e.value.status == EINVAL
+    vals[1] = 0.0                               # the second slot unused: accepted
+    pf.load(keys, vals, np.zeros(Vf))
+    pf.steps(0)
+    k, v = pf.state()
+    assert torch.all(k[0] == 3) and torch.all(v[0] == 0.5) and torch.all(v[1] == 0)
+    with pytest.raises(FftevpError) as e:
+        pf.refine(np.full(8, 1 << 30), np.zeros(8))
+    assert e.value.status == EINVAL
+    with pytest.raises(FftevpError) as e:
+        pf.refine(np.zeros(8), np.full(8, np.nan))
+    assert e.value.status == EINVAL
+    with pytest.raises(FftevpError):
+        pf.steps(-1)
+    pf.close()
+
+
+def test_fullsize_sampled_windows(require_gpu):
+    """128^3 mechanical grid (256^3 PF points), 500 grains with nuclei: after
+    n steps a PF point depends only on the points within n face-steps, so the
+    oracle, run on the (2n + 1)^3 periodic window around a sampled point,
+    reproduces that point exactly."""
+    import torch
+    from paper_1509_04953_amd import PhaseField
+    shape = (128, 128, 128)
+    n = 4
+    grains, E = inputs(shape, 500, 330, nuclei=0.05)
+    pf = PhaseField(shape, K=6, threshold=1e-5)
+    pf.refine(grains, E)
+    pf.steps(n)
+    k, v = pf.state()
+    N = 256
+    rng = np.random.default_rng(331)
+    # half of the samples on grain boundaries, where the order parameters move
+    g3 = grains.reshape(128, 128, 128)
+    gb = np.zeros(g3.shape, dtype=bool)
+    for ax in range(3):
+        gb |= g3 != np.roll(g3, 1, axis=ax)
+    gbi = np.flatnonzero(gb)
+    cz = np.concatenate([gbi[rng.integers(gbi.size, size=24)], rng.integers(128 ** 3, size=24)])
+    pts = []
+    for c in cz:
+        z, y, x = np.unravel_index(c, (128, 128, 128))
+        pts.append((2 * z + rng.integers(2), 2 * y + rng.integers(2), 2 * x + rng.integers(2)))
+    pts = np.array(pts)
+    flat = torch.as_tensor((pts[:, 0] * N + pts[:, 1]) * N + pts[:, 2], device="cuda")
+    kg = k[:, flat].cpu().numpy()
+    vg = v[:, flat].cpu().numpy()
+    gf = OPF.refine_grain(grains, shape).reshape(N, N, N)
+    Ef = OPF.refine_linear(E, shape).reshape(N, N, N)
+    w = 2 * n + 1
+    off = np.arange(-n, n + 1)
+    cfg = OPF.PF(K=6, threshold=1e-5)
+    worst = 0.0
+    for s, (Z, Y, X) in enumerate(pts):
+        zi, yi, xi = (Z + off) % N, (Y + off) % N, (X + off) % N
+        gw = gf[np.ix_(zi, yi, xi)].reshape(-1)
+        ew = Ef[np.ix_(zi, yi, xi)].reshape(-1)
+        kf = OPF.keys_of(gw)
+        keys = np.unique(kf)
+        eta = (kf[None, :] == keys[:, None]).astype(np.float64)
+        is_rex = (keys & 1) == 1
+        for _ in range(n):
+            eta = OPF.pf_step(eta, is_rex, ew, (w, w, w), cfg)
+        c = (n * w + n) * w + n
+        ref = {int(kk): val for kk, val in zip(keys, eta[:, c]) if val > 0}
+        got = {int(kk): val for kk, val in zip(kg[:, s], vg[:, s]) if val > 0}
+        assert set(ref) == set(got), (s, ref, got)
+        for kk in ref:
+            worst = max(worst, abs(ref[kk] - got[kk]))
+    print(f"pf 256^3 sampled windows: max |diff| {worst:.2e}")
+    assert worst < TOL64
+    # the whole field: counts within K, values above the threshold, sorted
+    used = v > 0
+    assert bool(torch.all(v[used] > 1e-5))
+    assert bool(torch.all(v[:-1] >= v[1:]))
+    pf.close()
