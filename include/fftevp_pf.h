@@ -104,6 +104,37 @@ fftevp_status fftevp_pf_export(fftevp_pf* pf, int* keys_dev, double* vals_dev);
  * grain_before_dev, grain_out_dev: int32 [V]; they may be the same buffer. */
 fftevp_status fftevp_pf_grains(fftevp_pf* pf, const int* grain_before_dev, int* grain_out_dev);
 
+/* The mechanical grid the context refines (host ints). */
+fftevp_status fftevp_pf_dims(const fftevp_pf* pf, int* n0, int* n1, int* n2);
+
+/* Number of PF steps that fit in a mechanical increment dt (s):
+ * floor(dt / (0.225 omega_gb / M_gb)) (Sec. 2.4), omega_gb in J/m^2, M_gb in
+ * m^4/(J s); -1 if an argument is not finite and positive or the count
+ * exceeds 2^31 - 1. */
+int fftevp_pf_step_count(double dt, double omega_gb, double mobility);
+
+/* Grain growth after nucleation, on the mechanical solver's committed state
+ * (Sec. 2.4-2.5): the stored energy E_store = rho_tot zeta mu b^2 of every
+ * voxel (rho_tot as in fftevp_drx_nucleate, Eq. 11; mu and b of
+ * fftevp_set_material, MPa and m) in units of 6 omega_gb / (sqrt(9.6) dx),
+ * refinement of it and of the grain map onto pf (fftevp_pf_refine), nsteps
+ * steps, and the grain map read back (fftevp_pf_grains). Voxels whose grain
+ * changed to a recrystallised one (negative id) keep s_soften of their GND
+ * densities (Eq. 16, as points of a new grain; SSD densities, orientation
+ * and nucleation strength unchanged). With orientations inherited the
+ * elastic moduli do not change, so the stress needs no re-solve here.
+ * n_changed (may be NULL): voxels whose grain changed; n_rex (may be NULL):
+ * of those, the ones now recrystallised. ESTATE unless DRX nucleation is
+ * enabled on ctx; EINVAL if pf refines another grid, zeta, omega_gb or dx
+ * is not finite and positive, or nsteps < 0. */
+typedef struct {
+  double zeta;      /* stored-energy constant (Table 2)            */
+  double omega_gb;  /* grain-boundary energy, J/m^2 (Table 2)      */
+  double dx;        /* PF grid spacing, m (half the voxel size)    */
+} fftevp_grow;
+fftevp_status fftevp_drx_grow(fftevp_ctx* ctx, fftevp_pf* pf, const fftevp_grow* p, int nsteps,
+                              long long* n_changed, long long* n_rex);
+
 const char* fftevp_pf_last_error(const fftevp_pf* pf);
 
 #ifdef __cplusplus

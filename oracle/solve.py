@@ -39,6 +39,7 @@ from . import local as L
 from .crystal import voxel_material
 from . import drx as DX
 from . import ma_roters as MR
+from . import pf as PF
 from .gnd import gnd_rates, next_leff
 from .green import gamma_field, green_apply
 from .tensors import (isotropic_c4, mandel_to_voigt, voigt_to_mandel, c4_to_mandel)
@@ -135,6 +136,33 @@ class Oracle:
         G["rs"] = np.where(hit[None], self.drx.s_soften * G["rs"], G["rs"])
         G["ret"] = np.where(hit[None], self.drx.s_soften * G["ret"], G["ret"])
         return int(hit.sum())
+
+    def drx_grow(self, nsteps, zeta, omega_gb, dx, K=6, threshold=1e-5):
+        """Grain growth after nucleation (Sec. 2.4-2.5, see oracle.pf): stored
+        energy rho_tot zeta mu b^2 in units of 6 omega / (sqrt(9.6) dx), PF
+        steps on the 2:1 grid, grain map read back; voxels now in a
+        recrystallised grain they did not belong to keep s_soften of their
+        GND densities (Eq. 16; reading: they are points of a new grain).
+        Returns (changed, now recrystallised) voxel counts."""
+        G = self.gnd
+        k = DX.total_density(self.rho, G["rs"], G["ret"], self.mr,
+                             None if self.mr is None else self.ssd)
+        unit = 6.0 * omega_gb / (np.sqrt(9.6) * dx)
+        E = k * zeta * self.flow.mu * 1e6 * self.flow.b ** 2 / unit
+        keys, eta = PF.initial_state(G["grains"], self.shape)
+        Ef = PF.refine_linear(E, self.shape)
+        is_rex = (keys & 1) == 1
+        cfg = PF.PF(omega=omega_gb, zeta=zeta, K=K, threshold=threshold)
+        fine = tuple(2 * s for s in self.shape)
+        for _ in range(nsteps):
+            eta = PF.pf_step(eta, is_rex, Ef, fine, cfg)
+        new = PF.coarse_grains(keys, eta, self.shape, G["grains"])
+        changed = new != G["grains"]
+        soft = changed & (new < 0)
+        G["rs"] = np.where(soft[None], self.drx.s_soften * G["rs"], G["rs"])
+        G["ret"] = np.where(soft[None], self.drx.s_soften * G["ret"], G["ret"])
+        G["grains"] = new
+        return int(changed.sum()), int(soft.sum())
 
     def enable_mr(self, law=None):
         """Use the paper's own flow rule and SSD evolution (Sec. 2.2, Eq. 3-6;

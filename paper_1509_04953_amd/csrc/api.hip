@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/fftevp.h"
+#include "../../include/fftevp_pf.h"
 #include "kernels.h"
 
 using namespace fftevp;
@@ -42,6 +43,7 @@ struct Bufs {
   // DRX nucleation (allocated by set_drx)
   void* kappa = nullptr;   // nucleation strength, [V]
   int* grain2 = nullptr;   // second grain-id buffer, [V]
+  double* estore = nullptr;  // stored energy for grain growth, [V]
 };
 
 }  // namespace
@@ -306,6 +308,7 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.sysp);
   f(ctx->b.kappa);
   f(ctx->b.grain2);
+  f(ctx->b.estore);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->b.a_eta);
   f(ctx->b.a_sigt);
@@ -939,6 +942,69 @@ fftevp_status fftevp_drx_nucleate(fftevp_ctx* ctx, const double* u_dev, long lon
   std::swap(ctx->b.grain, ctx->b.grain2);
   if (n_nuclei) *n_nuclei = (long long)ctx->red2_h[0];
   // the paper's law: GND densities changed, so do the next parameters
+  if (ctx->law == 1) {
+    HIPCHK(mr_params(ctx));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  return FFTEVP_OK;
+}
+
+fftevp_status fftevp_drx_grow(fftevp_ctx* ctx, fftevp_pf* pf, const fftevp_grow* p, int nsteps,
+                              long long* n_changed, long long* n_rex) {
+  if (!ctx || !pf || !p) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (!ctx->drx_on) return fail(ctx, FFTEVP_ESTATE, "DRX nucleation is not enabled (fftevp_set_drx)");
+  if (!ctx->state_ok)
+    return fail(ctx, FFTEVP_ESTATE, "an adjoint solve reused the state buffers: load a snapshot first");
+  int d0 = 0, d1 = 0, d2 = 0;
+  (void)fftevp_pf_dims(pf, &d0, &d1, &d2);
+  if (d0 != ctx->n0 || d1 != ctx->n1 || d2 != ctx->n2)
+    return fail(ctx, FFTEVP_EINVAL, "the phase-field context refines another grid");
+  auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+  if (!pos(p->zeta) || !pos(p->omega_gb) || !pos(p->dx) || nsteps < 0)
+    return fail(ctx, FFTEVP_EINVAL, "zeta, omega_gb, dx must be finite and positive, nsteps >= 0");
+  const size_t V = ctx->V;
+  if (!ctx->b.estore && hipMalloc((void**)&ctx->b.estore, V * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
+  }
+  // E_store in J/m^3 (mu in MPa), then in units of 6 omega / (sqrt(9.6) dx)
+  const double unit = 6.0 * p->omega_gb / (std::sqrt(9.6) * p->dx);
+  const double scale = p->zeta * ctx->flow.mu * 1e6 * ctx->flow.b * ctx->flow.b / unit;
+  auto args = [&](auto tag) {
+    using T = decltype(tag);
+    DrxArgs<T> a{};
+    a.grain = ctx->b.grain;
+    a.grain_out = ctx->b.grain2;
+    a.gs = (T*)ctx->b.gnds;
+    a.ge = (T*)ctx->b.gndet;
+    a.ssd = (const T*)ctx->b.ssd;
+    a.rho = (const T*)ctx->b.rho;
+    a.partial = ctx->partial;
+    a.V = V;
+    a.n0 = ctx->n0;
+    a.n1 = ctx->n1;
+    a.n2 = ctx->n2;
+    a.rhom_c = ctx->mrc.rhom_c;
+    a.s_soften = ctx->drx.s_soften;
+    return a;
+  };
+  const bool mr = ctx->law == 1;
+  if (ctx->prec == FFTEVP_FP64) HIPCHK(launch_rho_tot<double>(args(double{}), mr, scale, ctx->b.estore, ctx->stream));
+  else HIPCHK(launch_rho_tot<float>(args(float{}), mr, scale, ctx->b.estore, ctx->stream));
+  auto pf_call = [&](fftevp_status st) {
+    return st == FFTEVP_OK ? st : fail(ctx, st, std::string("phase field: ") + fftevp_pf_last_error(pf));
+  };
+  fftevp_status st = pf_call(fftevp_pf_refine(pf, ctx->b.grain, ctx->b.estore));
+  if (st == FFTEVP_OK) st = pf_call(fftevp_pf_steps(pf, nsteps));
+  if (st == FFTEVP_OK) st = pf_call(fftevp_pf_grains(pf, ctx->b.grain, ctx->b.grain2));
+  if (st != FFTEVP_OK) return st;
+  if (ctx->prec == FFTEVP_FP64) HIPCHK(launch_sweep<double>(args(double{}), ctx->red_nb, ctx->red2, ctx->stream));
+  else HIPCHK(launch_sweep<float>(args(float{}), ctx->red_nb, ctx->red2, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::swap(ctx->b.grain, ctx->b.grain2);
+  if (n_changed) *n_changed = (long long)ctx->red2_h[0];
+  if (n_rex) *n_rex = (long long)ctx->red2_h[1];
   if (ctx->law == 1) {
     HIPCHK(mr_params(ctx));
     HIPCHK(hipStreamSynchronize(ctx->stream));

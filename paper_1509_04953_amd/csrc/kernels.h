@@ -211,6 +211,13 @@ hipError_t launch_kappa(const double* u, T* kappa, size_t V, double kc, double q
                         double* out2, hipStream_t s);
 template <typename T>
 hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, hipStream_t s);
+// scale x total dislocation density (Eq. 11) of every voxel into out [V]
+template <typename T>
+hipError_t launch_rho_tot(const DrxArgs<T>& a, bool mr, double scale, double* out, hipStream_t s);
+// grain ids a.grain (before) vs a.grain_out (after growth): counts of changed
+// voxels and of those now in recrystallised grains into out2, GND softening
+template <typename T>
+hipError_t launch_sweep(const DrxArgs<T>& a, int nblocks, double* out2, hipStream_t s);
 hipError_t launch_export_int(const int* src, double* dst, size_t V, hipStream_t s);
 template <typename T>
 hipError_t launch_mr_params(const T* ssd, const T* gnds, const T* gndet, T* sysp, size_t V, const MrConst& c,

@@ -1099,13 +1099,35 @@ __global__ __launch_bounds__(256) void k_kappa(const double* __restrict__ u, T* 
   block_reduce<2, 0>(bad, partial + (size_t)blockIdx.x * 2);
 }
 
+// Total dislocation density of voxel g (Eq. 11): per-system SSD + GND (sqrt
+// of screw^2 + edge^2) + mobile for the paper's law; the voxel density + GND
+// for the power law.
+template <typename T, bool MRLAW>
+__device__ __forceinline__ double drx_total_density(const DrxArgs<T>& a, size_t g) {
+  const size_t V = a.V;
+  double k = 0.0;
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    const double gs = a.gs[(size_t)al * V + g], ge = a.ge[(size_t)al * V + g];
+    k += sqrt(gs * gs + ge * ge);
+  }
+  if constexpr (MRLAW) {
+    double F[12], P[12];
+    mr_projections(a.ssd, a.gs, a.ge, V, g, F, P);
+#pragma unroll
+    for (int al = 0; al < 12; ++al) k += (double)a.ssd[(size_t)al * V + g] + a.rhom_c * sqrt(P[al] * F[al]);
+  } else {
+    k += (double)a.rho[g];
+  }
+  return k;
+}
+
 // One nucleation test on the state after an increment: a voxel with a face
 // neighbour of another grain nucleates when its total dislocation density
-// (Eq. 11: per-system SSD + GND (sqrt of screw^2 + edge^2) + mobile for the
-// paper's law; the voxel density + GND for the power law) exceeds its
-// strength. A nucleus becomes a single-voxel grain (id -(index + 1)), keeps
-// s_soften of its GND densities (Eq. 16) and draws a new strength with
-// s_nucl kc. Grain ids are read from one buffer and written to another.
+// exceeds its strength. A nucleus becomes a single-voxel grain (id
+// -(index + 1)), keeps s_soften of its GND densities (Eq. 16) and draws a new
+// strength with s_nucl kc. Grain ids are read from one buffer and written to
+// another.
 template <typename T, bool MRLAW>
 __global__ __launch_bounds__(256) void k_drx(DrxArgs<T> a) {
   const size_t V = a.V;
@@ -1123,20 +1145,7 @@ __global__ __launch_bounds__(256) void k_drx(DrxArgs<T> a) {
     for (int k = 0; k < 6; ++k) site |= a.grain[nb[k]] != me;
     int out = me;
     if (site) {
-      double k = 0.0;
-#pragma unroll
-      for (int al = 0; al < 12; ++al) {
-        const double gs = a.gs[(size_t)al * V + g], ge = a.ge[(size_t)al * V + g];
-        k += sqrt(gs * gs + ge * ge);
-      }
-      if constexpr (MRLAW) {
-        double F[12], P[12];
-        mr_projections(a.ssd, a.gs, a.ge, V, g, F, P);
-#pragma unroll
-        for (int al = 0; al < 12; ++al) k += (double)a.ssd[(size_t)al * V + g] + a.rhom_c * sqrt(P[al] * F[al]);
-      } else {
-        k += (double)a.rho[g];
-      }
+      const double k = drx_total_density<T, MRLAW>(a, g);
       if (k > (double)a.kappa[g]) {
         out = -(int)(g + 1);
         cnt[0] += 1.0;
@@ -1149,6 +1158,38 @@ __global__ __launch_bounds__(256) void k_drx(DrxArgs<T> a) {
       }
     }
     a.grain_out[g] = out;
+  }
+  block_reduce<2, 0>(cnt, a.partial + (size_t)blockIdx.x * 2);
+}
+
+// scale x total dislocation density of every voxel (the stored energy
+// E_store = rho_tot zeta mu b^2 of Eq. 14, in the units the scale gives)
+template <typename T, bool MRLAW>
+__global__ __launch_bounds__(256) void k_rho_tot(DrxArgs<T> a, double scale, double* __restrict__ out) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < a.V; g += (size_t)gridDim.x * 256)
+    out[g] = scale * drx_total_density<T, MRLAW>(a, g);
+}
+
+// After grain growth: voxels whose grain changed are counted; those now in a
+// recrystallised grain (negative id) keep s_soften of their GND densities
+// (Eq. 16, as material points of a new grain).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep(DrxArgs<T> a) {
+  const size_t V = a.V;
+  double cnt[2] = {0.0, 0.0};
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    const int before = a.grain[g], after = a.grain_out[g];
+    if (after != before) {
+      cnt[0] += 1.0;
+      if (after < 0) {
+        cnt[1] += 1.0;
+#pragma unroll
+        for (int al = 0; al < 12; ++al) {
+          a.gs[(size_t)al * V + g] = (T)(a.s_soften * (double)a.gs[(size_t)al * V + g]);
+          a.ge[(size_t)al * V + g] = (T)(a.s_soften * (double)a.ge[(size_t)al * V + g]);
+        }
+      }
+    }
   }
   block_reduce<2, 0>(cnt, a.partial + (size_t)blockIdx.x * 2);
 }
@@ -1525,6 +1566,20 @@ hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, h
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_rho_tot(const DrxArgs<T>& a, bool mr, double scale, double* out, hipStream_t s) {
+  if (mr) hipLaunchKernelGGL((k_rho_tot<T, true>), dim3(grid_for(a.V)), dim3(256), 0, s, a, scale, out);
+  else hipLaunchKernelGGL((k_rho_tot<T, false>), dim3(grid_for(a.V)), dim3(256), 0, s, a, scale, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep(const DrxArgs<T>& a, int nblocks, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_sweep<T>, dim3(nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, s, (const double*)a.partial, nblocks, out2);
+  return hipGetLastError();
+}
+
 hipError_t launch_export_int(const int* src, double* dst, size_t V, hipStream_t s) {
   hipLaunchKernelGGL(k_export_int<double>, dim3(grid_for(V)), dim3(256), 0, s, src, dst, V);
   return hipGetLastError();
@@ -1584,6 +1639,8 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_kappa<T>(const double*, T*, size_t, double, double, double*, int, double*, \
                                       hipStream_t);                                           \
   template hipError_t launch_drx<T>(const DrxArgs<T>&, bool, int, double*, hipStream_t);      \
+  template hipError_t launch_rho_tot<T>(const DrxArgs<T>&, bool, double, double*, hipStream_t); \
+  template hipError_t launch_sweep<T>(const DrxArgs<T>&, int, double*, hipStream_t);          \
   template hipError_t launch_mr_params<T>(const T*, const T*, const T*, T*, size_t, const MrConst&, \
                                           hipStream_t);                                       \
   template hipError_t launch_gdot_mr<T>(const T*, const T*, const T*, double*, size_t, hipStream_t); \

@@ -609,6 +609,22 @@ fftevp_status fftevp_pf_grains(fftevp_pf* pf, const int* grain_before_dev, int* 
   return FFTEVP_OK;
 }
 
+fftevp_status fftevp_pf_dims(const fftevp_pf* pf, int* n0, int* n1, int* n2) {
+  if (!pf || !n0 || !n1 || !n2) return FFTEVP_EINVAL;
+  *n0 = pf->n0;
+  *n1 = pf->n1;
+  *n2 = pf->n2;
+  return FFTEVP_OK;
+}
+
+int fftevp_pf_step_count(double dt, double omega_gb, double mobility) {
+  if (!(std::isfinite(dt) && dt > 0.0 && std::isfinite(omega_gb) && omega_gb > 0.0 &&
+        std::isfinite(mobility) && mobility > 0.0))
+    return -1;
+  const double n = std::floor(dt / (0.225 * omega_gb / mobility));
+  return n < 2147483647.0 ? (int)n : -1;
+}
+
 const char* fftevp_pf_last_error(const fftevp_pf* pf) { return pf ? pf->err.c_str() : "null context"; }
 
 }  // extern "C"

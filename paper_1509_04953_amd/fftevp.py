@@ -39,6 +39,10 @@ class DrxC(C.Structure):
     _fields_ = [("kc", C.c_double), ("q", C.c_double), ("s_nucl", C.c_double), ("s_soften", C.c_double)]
 
 
+class GrowC(C.Structure):
+    _fields_ = [("zeta", C.c_double), ("omega_gb", C.c_double), ("dx", C.c_double)]
+
+
 class FlowC(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("tau0", "k1", "k2", "n", "gdot0", "alpha", "mu", "b")]
 
@@ -98,6 +102,9 @@ def library():
         "fftevp_pf_export": (I, [P, P, P]),
         "fftevp_pf_grains": (I, [P, P, P]),
         "fftevp_pf_last_error": (C.c_char_p, [P]),
+        "fftevp_pf_dims": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+        "fftevp_pf_step_count": (I, [C.c_double, C.c_double, C.c_double]),
+        "fftevp_drx_grow": (I, [P, P, C.POINTER(GrowC), I, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -260,6 +267,15 @@ class Solver:
         n = C.c_longlong(0)
         self._check(self.lib.fftevp_drx_nucleate(self.h, C.c_void_p(t.data_ptr()), C.byref(n)))
         return int(n.value)
+
+    def drx_grow(self, pf: "PhaseField", nsteps: int, zeta: float = 0.25, omega_gb: float = 0.625,
+                 dx: float = 10.7e-6):
+        """Grain growth on ``pf`` after nucleation; returns (voxels whose grain
+        changed, of those now recrystallised)."""
+        a, b = C.c_longlong(0), C.c_longlong(0)
+        self._check(self.lib.fftevp_drx_grow(self.h, pf.h, C.byref(GrowC(zeta, omega_gb, dx)), int(nsteps),
+                                             C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
 
     def set_gnd(self, grains, l0: float = 21.4e-6, xi: float = 200.0):
         """Track GND densities (screw and edge, per slip system) from every
