@@ -217,6 +217,51 @@ def run_drx(w, quat, rho, grains, precision, tests=4):
     return {"precision": precision, "ms_per_test": dt * 1e3, "nuclei": n}
 
 
+def run_pf(w, grains, precision, steps=200, warmup=100, K=6):
+    """Phase-field grain growth (Sec. 2.4) on the 2:1 grid of the workload
+    (one PF point per eighth of a voxel): grain map with one-voxel nuclei on
+    5% of the boundary voxels, stored energy log-normal with median 0.7 in
+    PF units (rho_tot ~ 1e14 m^-2 at the paper's voxel size). ``warmup``
+    steps let the sharp boundaries relax first; then ``steps`` steps are
+    timed with HIP events on the stream the kernels run on. Algorithmic
+    bytes per step: per point, the count byte and the used (key, value)
+    slots read and written once, plus the stored energy where both kinds of
+    order parameter meet (the only points that read it)."""
+    import torch
+    import synth
+    from paper_1509_04953_amd import PhaseField
+    rng = np.random.default_rng(w.seed + 1000)
+    g = synth.single_voxel_nuclei(grains, 0.05, rng).reshape(-1)
+    E = synth.lognormal_rho(w.shape, 0.7, 0.3, rng).reshape(-1)
+    pf = PhaseField(w.shape, K=K, threshold=1e-5, precision=precision)
+    pf.refine(g, E)
+    pf.steps(warmup)
+    k, v = pf.state()
+    used = v > 0
+    c = used.sum(0).double()
+    rex = (used & ((k & 1) == 1)).any(0)
+    dfm = (used & ((k & 1) == 0)).any(0)
+    word = 8 if precision == "fp64" else 4
+    nbytes = float(2 * (1 + c * (4 + word)).sum() + word * (rex & dfm).sum())
+    mean_slots = float(c.mean())
+    del k, v, used, c, rex, dfm
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    pf.steps(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    pf.close()
+    return {"precision": precision, "pf_points": 8 * w.voxels, "K": K, "steps": steps,
+            "warmup_steps": warmup, "ms_per_step": ms,
+            "point_steps_per_s": 8 * w.voxels / (ms * 1e-3), "mean_slots_per_point": mean_slots,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes}}
+
+
 def source_hash():
     """Prefix of the sha256 of the device sources (matches the profiles)."""
     import hashlib
@@ -344,6 +389,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-gnd", action="store_true")
     ap.add_argument("--no-mr", action="store_true")
+    ap.add_argument("--no-pf", action="store_true")
     ap.add_argument("--adjoint-workload", default="cu128adj")
     ap.add_argument("--adjoint-increments", type=int, default=0,
                     help="increments of the adjoint run (default: the workload's)")
@@ -414,6 +460,8 @@ def main():
         line["drx"] = run_drx(w, quat, rho, grains, precs[0])
     if not args.no_mr:
         line["paper_law"] = {p: run_mr(w, quat, rho, p) for p in precs}
+    if not args.no_pf:
+        line["phase_field"] = {p: run_pf(w, grains, p) for p in precs}
     if not args.no_adjoint:
         wa = synth.workload(args.adjoint_workload)
         if wa.name == w.name:

@@ -174,10 +174,13 @@ __global__ __launch_bounds__(kBlock) void k_pf_step(StepArgs<T> a) {
       const int q = ok[i];
       T lap = T(-6) * e;
 #pragma unroll
-      for (int n = 0; n < 6; ++n)
+      for (int n = 0; n < 6; ++n) {
+        T w = T(0);  // value of q at neighbour n (at most one slot matches)
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (j < kmax) lap += nk[n][j] == q ? nv[n][j] : T(0);
+        for (int j = K - 1; j >= 0; --j)
+          if (j < kmax) w = nk[n][j] == q ? nv[n][j] : w;
+        lap += w;
+      }
       const T e2 = e * e;
       const T well = e2 * e - e + T(3) * e * (s2 - e2);
       const T dF = well - T(kGrad) * lap + ((q & 1) ? dfr : dfd) * e;
@@ -188,6 +191,11 @@ __global__ __launch_bounds__(kBlock) void k_pf_step(StepArgs<T> a) {
       }
     }
   }
+  // a candidate enters the list unless the list is full and it ranks below
+  // the last entry
+  auto enters = [&](T v, int q) {
+    return used < K || v > tv[K - 1] || (v == tv[K - 1] && q < tk[K - 1]);
+  };
   // order parameters that diffuse in: zero here, so only the Laplacian acts
 #pragma unroll
   for (int n = 0; n < 6; ++n) {
@@ -199,24 +207,29 @@ __global__ __launch_bounds__(kBlock) void k_pf_step(StepArgs<T> a) {
 #pragma unroll
         for (int i = 0; i < K; ++i)
           if (i < kmax) fresh = fresh && q != ok[i];
+        if (!wave_any(fresh)) continue;
 #pragma unroll
         for (int m = 0; m < n; ++m)
 #pragma unroll
           for (int jj = 0; jj < K; ++jj)
             if (jj < kmax) fresh = fresh && q != nk[m][jj];
-        if (wave_any(fresh)) {
-          T s = nv[n][j];
+        if (!wave_any(fresh)) continue;
+        // value of q at the later neighbours: at most one slot each matches
+        T s = nv[n][j];
 #pragma unroll
-          for (int m = n + 1; m < 6; ++m)
+        for (int m = n + 1; m < 6; ++m) {
+          T w = T(0);
 #pragma unroll
-            for (int jj = 0; jj < K; ++jj)
-              if (jj < kmax) s += nk[m][jj] == q ? nv[m][jj] : T(0);
-          const T v = T(kKin) * (T(kGrad) * s);
-          if (fresh && v > a.thr) {
-            keep_largest(tv, tk, v, q);
-            ++used;
-          }
+          for (int jj = K - 1; jj >= 0; --jj)
+            if (jj < kmax) w = nk[m][jj] == q ? nv[m][jj] : w;
+          s += w;
         }
+        const T v = T(kKin) * (T(kGrad) * s);
+        const bool cand = fresh && v > a.thr;
+        if (wave_any(cand && enters(v, q))) {
+          if (cand) keep_largest(tv, tk, v, q);
+        }
+        used += cand ? 1 : 0;
       }
     }
   }
