@@ -258,28 +258,32 @@ def run_pf(w, grains, precision, steps=200, warmup=100, K=6):
     summary = "phasefield_256cube_k_pf_step.md"
     full = w.shape == (128, 128, 128) and K == 6
     prec = "fp64" if precision == "fp64" else "mixed"
-    issue = stored_valu_issue_us("k_pf_step", prec, summary) if full else None
+    issue = stored_valu_issue_us("k_pf_step", prec, summary, PF_SOURCES) if full else None
     return {"precision": precision, "pf_points": 8 * w.voxels, "K": K, "steps": steps,
             "warmup_steps": warmup, "ms_per_step": ms,
             "point_steps_per_s": 8 * w.voxels / (ms * 1e-3), "mean_slots_per_point": mean_slots,
             "roofline": {"kernel": "k_pf_step", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes,
-                         "traffic": stored_traffic("k_pf_step", prec, summary) if full else None,
+                         "traffic": stored_traffic("k_pf_step", prec, summary, PF_SOURCES) if full else None,
                          # limited by vector-ALU issue (candidate matching), not by HBM
                          "valu_issue_frac": (issue * 1e-3 / ms) if issue else None}}
 
 
-def source_hash():
-    """Prefix of the sha256 of the device sources (matches the profiles)."""
+FFTEVP_SOURCES = ("kernels.hip", "device_math.h", "fft_lds.h")
+PF_SOURCES = ("phasefield.hip",)
+
+
+def source_hash(files=FFTEVP_SOURCES):
+    """Prefix of the sha256 of device sources (matches the profiles)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_math.h", "fft_lds.h", "phasefield.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1509_04953_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel, precision, summary="fftevp_128cube_hbm_traffic.md"):
+def stored_traffic(kernel, precision, summary="fftevp_128cube_hbm_traffic.md", files=FFTEVP_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     or None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", summary)
@@ -287,7 +291,7 @@ def stored_traffic(kernel, precision, summary="fftevp_128cube_hbm_traffic.md"):
         lines = open(path).read().splitlines()
     except OSError:
         return None
-    src = source_hash()
+    src = source_hash(files)
     for ln in lines:
         f = ln.split()
         if len(f) >= 3 and f[0] == "traffic" and f[1] == kernel and f[2] == precision:
@@ -299,7 +303,7 @@ def stored_traffic(kernel, precision, summary="fftevp_128cube_hbm_traffic.md"):
     return None
 
 
-def stored_valu_issue_us(kernel, precision, summary="fftevp_128cube_sq_counters.md"):
+def stored_valu_issue_us(kernel, precision, summary="fftevp_128cube_sq_counters.md", files=FFTEVP_SOURCES):
     """VALU issue time per launch (us) from the committed shader-counter
     summary: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz); None when
     the kernel sources changed since the counters were taken."""
@@ -308,7 +312,7 @@ def stored_valu_issue_us(kernel, precision, summary="fftevp_128cube_sq_counters.
         lines = open(path).read().splitlines()
     except OSError:
         return None
-    src = source_hash()
+    src = source_hash(files)
     for ln in lines:
         f = ln.split()
         if len(f) >= 3 and f[0] == "valu" and f[1] == kernel and f[2] == precision:
