@@ -62,7 +62,8 @@ def test_refine_is_the_oracles(require_gpu):
     pf.close()
 
 
-@pytest.mark.parametrize("shape,steps", [((5, 6, 7), 40), ((8, 8, 8), 60), ((1, 1, 1), 5), ((3, 1, 2), 12)])
+@pytest.mark.parametrize("shape,steps", [((5, 6, 7), 40), ((8, 8, 8), 60), ((1, 1, 1), 5), ((3, 1, 2), 12),
+                                         ((32, 32, 4), 20)])
 def test_steps_match_oracle_fp64(require_gpu, shape, steps):
     from paper_1509_04953_amd import PhaseField
     grains, E = inputs(shape, 6, 302 + steps)
