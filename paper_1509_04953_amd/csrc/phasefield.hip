@@ -40,6 +40,24 @@ __device__ __forceinline__ int tile_base() {
   return (int)(id * kBlock);
 }
 
+// Tile order of the step: when a z-plane splits into 8 equal runs of whole
+// tiles, XCD x (blocks id = x mod 8) owns run x of every plane and walks
+// through the planes in z order, so the plane below a tile was read only a
+// run earlier (tens of tiles) and is still in that XCD's L2 when the tile
+// reads it as a neighbour; the plane above is being brought in by the tiles
+// that follow.
+__device__ __forceinline__ int step_tile_base(int n0, int n1, int n2) {
+  const unsigned plane = (unsigned)n0 * (unsigned)n1;
+  if (plane % (8u * kBlock) == 0) {
+    const unsigned ntp = plane / kBlock, run = ntp / 8;
+    if (gridDim.x == ntp * (unsigned)n2) {
+      const unsigned id = blockIdx.x, x = id % 8, k = id / 8;
+      return (int)(((k / run) * ntp + x * run + k % run) * kBlock);
+    }
+  }
+  return tile_base();
+}
+
 // Insert (v, k) into a list sorted by decreasing value (equal values: smaller
 // key first); the smallest entry falls off the end.
 template <typename T, int K>
@@ -76,7 +94,7 @@ struct StepArgs {
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_pf_step(StepArgs<T> a) {
   const int V = a.V;
-  const int p0 = tile_base() + (int)threadIdx.x;
+  const int p0 = step_tile_base(a.n0, a.n1, a.n2) + (int)threadIdx.x;
   const bool live = p0 < V;
   const int p = live ? p0 : V - 1;
   const int n0 = a.n0, n1 = a.n1, n2 = a.n2, pl = n0 * n1;
