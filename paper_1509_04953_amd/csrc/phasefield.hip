@@ -91,8 +91,10 @@ struct StepArgs {
 // the point or at one of its six neighbours (the others stay zero), then
 // truncation. The candidate keys are the point's own and, once each, those
 // its neighbours hold that it does not.
+// Occupancy: three waves per SIMD for FP64 (a few registers spill, which
+// costs less than the latency the extra wave hides), four for FP32.
 template <typename T, int K>
-__global__ __launch_bounds__(kBlock) void k_pf_step(StepArgs<T> a) {
+__global__ __launch_bounds__(kBlock, sizeof(T) == 8 ? 3 : 4) void k_pf_step(StepArgs<T> a) {
   const int V = a.V;
   const int p0 = step_tile_base(a.n0, a.n1, a.n2) + (int)threadIdx.x;
   const bool live = p0 < V;

@@ -160,17 +160,19 @@ def test_zero_steps_and_input_checks(require_gpu):
     pf.close()
 
 
-def test_fullsize_sampled_windows(require_gpu):
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", 1e-5)])
+def test_fullsize_sampled_windows(require_gpu, precision, tol):
     """128^3 mechanical grid (256^3 PF points), 500 grains with nuclei: after
     n steps a PF point depends only on the points within n face-steps, so the
     oracle, run on the (2n + 1)^3 periodic window around a sampled point,
-    reproduces that point exactly."""
+    reproduces that point exactly (FP32: to its rounding over n steps; keys
+    compared where the oracle's value is clear of the threshold)."""
     import torch
     from paper_1509_04953_amd import PhaseField
     shape = (128, 128, 128)
     n = 4
     grains, E = inputs(shape, 500, 330, nuclei=0.05)
-    pf = PhaseField(shape, K=6, threshold=1e-5)
+    pf = PhaseField(shape, K=6, threshold=1e-5, precision=precision)
     pf.refine(grains, E)
     pf.steps(n)
     k, v = pf.state()
@@ -210,11 +212,20 @@ def test_fullsize_sampled_windows(require_gpu):
         c = (n * w + n) * w + n
         ref = {int(kk): val for kk, val in zip(keys, eta[:, c]) if val > 0}
         got = {int(kk): val for kk, val in zip(kg[:, s], vg[:, s]) if val > 0}
-        assert set(ref) == set(got), (s, ref, got)
-        for kk in ref:
+        if precision == "fp64":
+            assert set(ref) == set(got), (s, ref, got)
+        else:
+            # a key held on one side only sits at the threshold or ties for
+            # the last of the K places within FP32 rounding
+            for kk in set(ref) ^ set(got):
+                val = ref.get(kk, got.get(kk))
+                other = got if kk in ref else ref
+                last = min(other.values()) if len(other) == 6 else 0.0
+                assert val < 2e-5 or val <= last * (1 + 1e-3) + 1e-6, (s, kk, ref, got)
+        for kk in set(ref) & set(got):
             worst = max(worst, abs(ref[kk] - got[kk]))
-    print(f"pf 256^3 sampled windows: max |diff| {worst:.2e}")
-    assert worst < TOL64
+    print(f"pf 256^3 {precision} sampled windows: max |diff| {worst:.2e}")
+    assert worst < tol
     # the whole field: counts within K, values above the threshold, sorted
     used = v > 0
     assert bool(torch.all(v[used] > 1e-5))
