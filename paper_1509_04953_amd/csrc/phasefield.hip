@@ -74,6 +74,27 @@ __device__ __forceinline__ void keep_largest(T (&tv)[K], int (&tk)[K], T v, int 
   }
 }
 
+// Order (tv, tk) by decreasing value, equal values by increasing key, with
+// the 12-comparator sorting network for six inputs (cheaper than inserting
+// the six one by one).
+template <typename T>
+__device__ __forceinline__ void sort6(T (&tv)[6], int (&tk)[6]) {
+  auto cx = [&](int i, int j) {
+    const bool sw = tv[j] > tv[i] || (tv[j] == tv[i] && tk[j] < tk[i]);
+    const T vi = tv[i], vj = tv[j];
+    const int ki = tk[i], kj = tk[j];
+    tv[i] = sw ? vj : vi;
+    tv[j] = sw ? vi : vj;
+    tk[i] = sw ? kj : ki;
+    tk[j] = sw ? ki : kj;
+  };
+  cx(0, 5); cx(1, 3); cx(2, 4);
+  cx(1, 2); cx(3, 4);
+  cx(0, 3); cx(2, 5);
+  cx(0, 1); cx(2, 3); cx(4, 5);
+  cx(1, 2); cx(3, 4);
+}
+
 template <typename T>
 struct StepArgs {
   const unsigned char* cnt;
@@ -205,12 +226,18 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 8 ? 3 : 4) void k_pf_step(Step
       const T well = e2 * e - e + T(3) * e * (s2 - e2);
       const T dF = well - T(kGrad) * lap + ((q & 1) ? dfr : dfd) * e;
       const T v = e - T(kKin) * dF;
-      if (i < c0 && v > a.thr) {
+      const bool keep = i < c0 && v > a.thr;
+      if constexpr (K == 6) {
+        // placed in slot order here, sorted by the network below
+        tv[i] = keep ? v : T(0);
+        tk[i] = keep ? q : INT_MAX;
+      } else if (keep) {
         keep_largest(tv, tk, v, q);
-        ++used;
       }
+      used += keep ? 1 : 0;
     }
   }
+  if constexpr (K == 6) sort6(tv, tk);
   // a candidate enters the list unless the list is full and it ranks below
   // the last entry
   auto enters = [&](T v, int q) {
