@@ -168,12 +168,14 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
 #ifndef FFTEVP_LOCAL_WAVES_F32
 #define FFTEVP_LOCAL_WAVES_F32 4
 #endif
-// the paper's flow rule holds more per-system state (exp, four parameters)
+// the paper's flow rule holds more per-system state (exp, four parameters);
+// its FP32 instance runs three waves per SIMD with a few spilled registers
+// (faster than two without: the third wave hides more latency)
 #ifndef FFTEVP_MR_WAVES
 #define FFTEVP_MR_WAVES 1
 #endif
 #ifndef FFTEVP_MR_WAVES_F32
-#define FFTEVP_MR_WAVES_F32 2
+#define FFTEVP_MR_WAVES_F32 3
 #endif
 
 // FLOW: the flow rule (FLOW_POWER, FLOW_POWER_INT when the rate exponent is
