@@ -217,6 +217,46 @@ def run_drx(w, quat, rho, grains, precision, tests=4):
     return {"precision": precision, "ms_per_test": dt * 1e3, "nuclei": n}
 
 
+def run_coupled(w, quat, rho, grains, precision, cycles=3, pf_steps=20):
+    """The coupled loop (Sec. 2.5) on the workload: per increment the
+    mechanical solve with GND tracking, the nucleation test, and pf_steps
+    phase-field steps on the 2:1 grid with the grain map written back. Host
+    wall time per phase (each phase ends with a synchronisation), stored
+    energy at a PF spacing of 1 mm so that nuclei grow."""
+    import torch
+    from paper_1509_04953_amd import Solver, PhaseField, Material, Load, Opts
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load(dt=w.dt))
+    s.set_gnd(grains.reshape(-1))
+    gen = torch.Generator(device="cuda").manual_seed(1)
+    s.set_drx(torch.rand(w.voxels, dtype=torch.float64, device="cuda", generator=gen), kc=4.0e12)
+    pf = PhaseField(w.shape, K=6, threshold=1e-5, precision=precision)
+    opts = Opts(tol=w.tol, max_iter=2000)
+    t = {"solve": 0.0, "nucleate": 0.0, "grow": 0.0}
+    log = []
+    for _ in range(cycles):
+        u = torch.rand(w.voxels, dtype=torch.float64, device="cuda", generator=gen)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.step(opts)
+        t1 = time.perf_counter()
+        n = s.drx_nucleate(u)
+        t2 = time.perf_counter()
+        ch, rex = s.drx_grow(pf, pf_steps, dx=1.0e-3)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t["solve"] += t1 - t0
+        t["nucleate"] += t2 - t1
+        t["grow"] += t3 - t2
+        log.append({"iters": r.iters, "nuclei": n, "changed": ch, "recrystallised": rex})
+    pf.close()
+    s.close()
+    return {"precision": precision, "cycles": cycles, "pf_steps": pf_steps,
+            "ms_per_cycle": {k: v / cycles * 1e3 for k, v in t.items()}, "log": log}
+
+
 def run_pf(w, grains, precision, steps=200, warmup=100, K=6):
     """Phase-field grain growth (Sec. 2.4) on the 2:1 grid of the workload
     (one PF point per eighth of a voxel): grain map with one-voxel nuclei on
@@ -473,6 +513,8 @@ def main():
         line["paper_law"] = {p: run_mr(w, quat, rho, p) for p in precs}
     if not args.no_pf:
         line["phase_field"] = {p: run_pf(w, grains, p) for p in precs}
+    if not args.no_pf and not args.no_gnd:
+        line["coupled"] = run_coupled(w, quat, rho, grains, precs[0])
     if not args.no_adjoint:
         wa = synth.workload(args.adjoint_workload)
         if wa.name == w.name:

@@ -277,6 +277,16 @@ class Solver:
                                              C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
 
+    def drx_cycle(self, pf: "PhaseField", u, pf_steps: int, opts: Opts | None = None, zeta: float = 0.25,
+                  omega_gb: float = 0.625, dx: float = 10.7e-6):
+        """One increment of the coupled loop (Sec. 2.5): the mechanical solve,
+        the nucleation test with fresh uniforms ``u``, then ``pf_steps`` steps
+        of grain growth. Returns (report, nuclei, changed, recrystallised)."""
+        r = self.step(opts, allow=(OK,))
+        n = self.drx_nucleate(u)
+        changed, rex = self.drx_grow(pf, pf_steps, zeta, omega_gb, dx)
+        return r, n, changed, rex
+
     def set_gnd(self, grains, l0: float = 21.4e-6, xi: float = 200.0):
         """Track GND densities (screw and edge, per slip system) from every
         committed increment on; ``grains`` holds one integer grain id per

@@ -171,3 +171,45 @@ def test_drx_grow_errors(require_gpu):
     assert lib.fftevp_pf_step_count(-1.0, 0.625, 145e-6) == -1
     other.close()
     pf.close()
+
+
+@pytest.mark.parametrize("law", ["power", "paper"])
+def test_coupled_loop_matches_oracle(require_gpu, law):
+    """Three increments of the coupled loop (Sec. 2.5): solve, nucleation,
+    12 growth steps, each against the oracle."""
+    from paper_1509_04953_amd import Solver, PhaseField, Material, MaRoters, Load, Opts
+    shape = (16, 16, 16)
+    V = 4096
+    g = [np.random.default_rng(s) for s in np.random.SeedSequence(71).spawn(4)]
+    grains = synth.voronoi_grains(shape, 8, g[0])
+    q = synth.random_quaternions(8, g[1])
+    quat = np.moveaxis(q[grains], -1, 0).reshape(4, -1).copy()
+    rho = synth.lognormal_rho(shape, 2.5e12, 0.3, g[2]).reshape(-1)
+    rng = np.random.default_rng(72)
+    u0 = rng.random(V)
+    s = Solver(shape)
+    s.set_material(Material())
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load())
+    s.set_gnd(grains.reshape(-1))
+    o = Oracle(shape, quat, rho)
+    o.enable_gnd(grains.reshape(-1), 21.4e-6, 200.0)
+    if law == "paper":
+        s.set_law(MaRoters())
+        o.enable_mr(OMR.MaRoters())
+    kc = 1.0e13 if law == "power" else 1.6e13
+    s.set_drx(u0, kc=kc)
+    o.enable_drx(ODX.DRX(kc=kc), u0)
+    pf = PhaseField(shape, K=6, threshold=1e-5)
+    for inc in range(3):
+        print(f"case: coupled {law} increment {inc}", flush=True)
+        u = rng.random(V)
+        r, n, changed, rex = s.drx_cycle(pf, u, 12, Opts(tol=1e-11, max_iter=3000), dx=1.0e-3)
+        ro = o.increment(Loading(), tol=1e-11, max_iter=3000)
+        no = o.drx_nucleate(u)
+        co = o.drx_grow(12, 0.25, 0.625, 1.0e-3)
+        assert r.iters == ro["iters"] and n == no and (changed, rex) == co, (inc, n, no, changed, rex, co)
+        assert np.array_equal(s.field("grain").cpu().numpy(), o.field("grain"))
+        for k in ("sigma", "rho_gnds", "rho_gndet"):
+            assert rel(s.field(k).cpu().numpy(), o.field(k)) < 1e-10, (inc, k)
+    pf.close()
