@@ -78,3 +78,18 @@ def test_pf_null_context_calls(lib):
     assert lib.fftevp_pf_grains(None, None, None) == -1
     assert lib.fftevp_pf_import(None, None, None, 1, None) == -1
     assert lib.fftevp_pf_last_error(None) == b"null context"
+
+
+def test_pf_step_count_on_the_host(lib):
+    """floor(dt / (0.225 omega / M)) (Sec. 2.4), -1 for bad arguments."""
+    lib.fftevp_pf_step_count.restype = C.c_int
+    lib.fftevp_pf_step_count.argtypes = [C.c_double] * 3
+    assert lib.fftevp_pf_step_count(1.0, 0.625, 145e-6) == 0          # one step lasts ~970 s
+    assert lib.fftevp_pf_step_count(1000.0, 0.625, 145e-6) == 1
+    assert lib.fftevp_pf_step_count(9.0, 1.0, 1.0) == 40              # 9 / 0.225
+    assert lib.fftevp_pf_step_count(0.0, 1.0, 1.0) == -1
+    assert lib.fftevp_pf_step_count(1.0, float("nan"), 1.0) == -1
+    assert lib.fftevp_pf_step_count(1e300, 1.0, 1.0) == -1            # beyond int range
+    n = C.c_int()
+    assert lib.fftevp_pf_dims(None, C.byref(n), C.byref(n), C.byref(n)) == -1
+    assert lib.fftevp_drx_grow(None, None, None, 1, None, None) == -1
