@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kNoKey = INT_MIN;  // key of an unused slot on export
 constexpr int kBlock = 256;
+constexpr int kList = 16;  // LDS list entries per thread in the step (see there)
 
 // Coefficients in the solver's units (dx = 1, one step dt = 1,
 // l_gb^2 = 9.6, 6 omega_gb = l_gb, M_gb = 0.0375 l_gb):
@@ -243,40 +244,85 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 8 ? 3 : 4) void k_pf_step(Step
   auto enters = [&](T v, int q) {
     return used < K || v > tv[K - 1] || (v == tv[K - 1] && q < tk[K - 1]);
   };
-  // order parameters that diffuse in: zero here, so only the Laplacian acts
+  // Order parameters that diffuse in: zero here, so only the Laplacian acts.
+  // The neighbour slots whose key the point lacks are appended, in neighbour
+  // order, to a list of the thread's own in LDS; the first entry with a key
+  // sums that key's values over the later entries (the same neighbour order
+  // as a full scan), so the work scales with the few such slots of the point
+  // rather than with all 6 K. A wave in which some point has more than
+  // kList such slots scans all slots instead.
+  __shared__ int lk[kList * kBlock];
+  __shared__ T lv[kList * kBlock];
+  const int tid = threadIdx.x;
+  int nf = 0;
 #pragma unroll
-  for (int n = 0; n < 6; ++n) {
+  for (int n = 0; n < 6; ++n)
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < K; ++j)
       if (j < kmax) {
         const int q = nk[n][j];
-        bool fresh = j < cn[n];
+        bool f = j < cn[n];
 #pragma unroll
         for (int i = 0; i < K; ++i)
-          if (i < kmax) fresh = fresh && q != ok[i];
-        if (!wave_any(fresh)) continue;
-#pragma unroll
-        for (int m = 0; m < n; ++m)
-#pragma unroll
-          for (int jj = 0; jj < K; ++jj)
-            if (jj < kmax) fresh = fresh && q != nk[m][jj];
-        if (!wave_any(fresh)) continue;
-        // value of q at the later neighbours: at most one slot each matches
-        T s = nv[n][j];
-#pragma unroll
-        for (int m = n + 1; m < 6; ++m) {
-          T w = T(0);
-#pragma unroll
-          for (int jj = K - 1; jj >= 0; --jj)
-            if (jj < kmax) w = nk[m][jj] == q ? nv[m][jj] : w;
-          s += w;
+          if (i < kmax) f = f && q != ok[i];
+        if (f) {
+          if (nf < kList) {
+            lk[nf * kBlock + tid] = q;
+            lv[nf * kBlock + tid] = nv[n][j];
+          }
+          ++nf;
         }
-        const T v = T(kKin) * (T(kGrad) * s);
-        const bool cand = fresh && v > a.thr;
-        if (wave_any(cand && enters(v, q))) {
-          if (cand) keep_largest(tv, tk, v, q);
+      }
+  if (!wave_any(nf > kList)) {
+    for (int e = 0; e < nf; ++e) {
+      const int q = lk[e * kBlock + tid];
+      bool first = true;
+      for (int f = 0; f < e; ++f) first = first && lk[f * kBlock + tid] != q;
+      if (!first) continue;
+      T s = lv[e * kBlock + tid];
+      for (int f = e + 1; f < nf; ++f)
+        if (lk[f * kBlock + tid] == q) s += lv[f * kBlock + tid];
+      const T v = T(kKin) * (T(kGrad) * s);
+      if (v > a.thr) {
+        if (enters(v, q)) keep_largest(tv, tk, v, q);
+        ++used;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        if (j < kmax) {
+          const int q = nk[n][j];
+          bool fresh = j < cn[n];
+#pragma unroll
+          for (int i = 0; i < K; ++i)
+            if (i < kmax) fresh = fresh && q != ok[i];
+          if (!wave_any(fresh)) continue;
+#pragma unroll
+          for (int m = 0; m < n; ++m)
+#pragma unroll
+            for (int jj = 0; jj < K; ++jj)
+              if (jj < kmax) fresh = fresh && q != nk[m][jj];
+          if (!wave_any(fresh)) continue;
+          // value of q at the later neighbours: at most one slot each matches
+          T s = nv[n][j];
+#pragma unroll
+          for (int m = n + 1; m < 6; ++m) {
+            T w = T(0);
+#pragma unroll
+            for (int jj = K - 1; jj >= 0; --jj)
+              if (jj < kmax) w = nk[m][jj] == q ? nv[m][jj] : w;
+            s += w;
+          }
+          const T v = T(kKin) * (T(kGrad) * s);
+          const bool cand = fresh && v > a.thr;
+          if (wave_any(cand && enters(v, q))) {
+            if (cand) keep_largest(tv, tk, v, q);
+          }
+          used += cand ? 1 : 0;
         }
-        used += cand ? 1 : 0;
       }
     }
   }
