@@ -231,3 +231,37 @@ def test_fullsize_sampled_windows(require_gpu, precision, tol):
     assert bool(torch.all(v[used] > 1e-5))
     assert bool(torch.all(v[:-1] >= v[1:]))
     pf.close()
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_many_diffusing_keys(require_gpu, shared):
+    """Points whose neighbours hold many keys they lack (up to all 36 slots):
+    beyond the step's per-thread list the step scans all slots; both paths
+    against the oracle. shared=True: neighbours share part of their keys."""
+    from paper_1509_04953_amd import PhaseField
+    shape = (2, 2, 2)
+    fine = (4, 4, 4)
+    Vf = 64
+    rng = np.random.default_rng(340 + shared)
+    if shared:
+        pool = np.arange(40) * 2 + 1
+        kin = np.stack([rng.choice(pool, size=6, replace=False) for _ in range(Vf)], axis=1)
+    else:
+        kin = (np.arange(Vf)[None, :] * 6 + np.arange(6)[:, None]) * 2   # disjoint per point
+    vals = rng.uniform(0.01, 0.3, size=(6, Vf))
+    Ef = rng.random(Vf)
+    keys = np.unique(kin)
+    eta = np.zeros((len(keys), Vf))
+    eta[np.searchsorted(keys, kin), np.arange(Vf)[None, :].repeat(6, axis=0)] = vals
+    pf = PhaseField(shape, K=6, threshold=1e-5)
+    pf.load(kin.astype(np.int32), vals, Ef)
+    is_rex = (keys & 1) == 1
+    cfg = OPF.PF(K=6, threshold=1e-5)
+    for step in range(3):
+        eta = OPF.pf_step(eta, is_rex, Ef, fine, cfg)
+        pf.steps(1)
+        d, _, _ = dense(pf, keys)
+        err = np.abs(d - eta).max()
+        assert err < TOL64, (step, err)
+        assert np.array_equal(d > 0, eta > 0), step
+    pf.close()
