@@ -495,6 +495,30 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 // length N in LDS (line stride N + 1).
 template <typename T, int N, int W>
 __device__ __forceinline__ void rows_to_lines(const cx<T>* __restrict__ src, size_t rs, cx<T>* sh) {
+  if constexpr (sizeof(T) == 4 && W % 2 == 0) {
+    // FP32: two complex values per 16-byte load (rows, strides and bases
+    // hold an even number of complex values, so every pair is aligned)
+    constexpr int TOT = N * W / 2, PER = (TOT + 255) / 256;
+    float4 v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int idx = threadIdx.x + 256 * b;
+      if (TOT % 256 == 0 || idx < TOT) {
+        const int e = 2 * idx, r = e / W, w = e - (e / W) * W;
+        v[b] = *reinterpret_cast<const float4*>(src + (size_t)r * rs + w);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int idx = threadIdx.x + 256 * b;
+      if (TOT % 256 == 0 || idx < TOT) {
+        const int e = 2 * idx, r = e / W, w = e - (e / W) * W;
+        sh[w * (N + 1) + r] = {v[b].x, v[b].y};
+        sh[(w + 1) * (N + 1) + r] = {v[b].z, v[b].w};
+      }
+    }
+    return;
+  }
   // every load of the thread is issued before the first LDS store, so the
   // HBM latencies overlap instead of adding up
   constexpr int TOT = N * W, PER = (TOT + 255) / 256;
@@ -518,6 +542,28 @@ __device__ __forceinline__ void rows_to_lines(const cx<T>* __restrict__ src, siz
 }
 template <typename T, int N, int W>
 __device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict__ dst, size_t rs) {
+  if constexpr (sizeof(T) == 4 && W % 2 == 0) {
+    constexpr int TOT = N * W / 2, PER = (TOT + 255) / 256;
+    float4 v[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int idx = threadIdx.x + 256 * b;
+      if (TOT % 256 == 0 || idx < TOT) {
+        const int e = 2 * idx, r = e / W, w = e - (e / W) * W;
+        const cx<T> z0 = sh[w * (N + 1) + r], z1 = sh[(w + 1) * (N + 1) + r];
+        v[b] = make_float4(z0.x, z0.y, z1.x, z1.y);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int idx = threadIdx.x + 256 * b;
+      if (TOT % 256 == 0 || idx < TOT) {
+        const int e = 2 * idx, r = e / W, w = e - (e / W) * W;
+        *reinterpret_cast<float4*>(dst + (size_t)r * rs + w) = v[b];
+      }
+    }
+    return;
+  }
   constexpr int TOT = N * W, PER = (TOT + 255) / 256;
   cx<T> v[PER];
 #pragma unroll
