@@ -265,3 +265,30 @@ def test_many_diffusing_keys(require_gpu, shared):
         assert err < TOL64, (step, err)
         assert np.array_equal(d > 0, eta > 0), step
     pf.close()
+
+
+def test_fullsize_sphere_follows_curvature_law(require_gpu):
+    """256^3 PF points: a spherical grain of radius 60 PF cells, made by the
+    2:1 refinement of a 128^3 grain map, shrinks with dR^2/dt = -4 M omega =
+    -0.24 per step (the property the oracle's scheme is pinned to), within
+    6 %."""
+    import torch
+    from paper_1509_04953_amd import PhaseField
+    n = 128
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((x - n / 2 + 0.25) ** 2 + (y - n / 2 + 0.25) ** 2 + (z - n / 2 + 0.25) ** 2)
+    grains = np.where(r < 30.0, 1, 0).astype(np.int32).reshape(-1)
+    pf = PhaseField((n, n, n), K=6, threshold=1e-5)
+    pf.refine(grains, np.zeros(n ** 3))
+    rec = []
+    for step in range(1, 501):
+        pf.steps(1)
+        if step % 100 == 0:
+            k, v = pf.state()
+            vs = float(v[k == 2].sum())          # key of grain 1 (deformed)
+            rec.append((step, (3 * vs / (4 * np.pi)) ** (2 / 3)))
+    rec = np.array(rec)
+    slope = np.polyfit(rec[:, 0], rec[:, 1], 1)[0]
+    print(f"pf 256^3 sphere: dR^2/dt {slope:.4f} per step (law -0.24)")
+    assert abs(slope / -0.24 - 1) < 0.06, slope
+    pf.close()
