@@ -1,0 +1,121 @@
+"""The largest configuration: 256^3, 2000 grains, 5 % of the voxels in
+low-density spherical nuclei on grain boundaries. Mixed precision checked by
+properties that hold at any size and on sampled voxels (oracle material and
+flow rule, one voxel at a time); the adjoint with increment checkpointing
+against central finite differences of the GPU forward (FP64) and the mixed
+adjoint against the FP64 one."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import local as L
+from oracle.crystal import voxel_material
+from oracle.tensors import voigt_to_mandel
+
+pytestmark = pytest.mark.gpu
+
+W = synth.workload("cu256")
+
+
+@pytest.fixture(scope="module")
+def micro():
+    q, rho, _ = synth.make_microstructure(W)
+    return q.reshape(4, -1), rho.reshape(-1)
+
+
+def test_256_mixed_properties(require_gpu, micro):
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    q, rho0 = micro
+    s = Solver(W.shape, "mixed")
+    s.set_material(Material())
+    s.set_microstructure(q, rho0)
+    s.set_loading(Load(dt=W.dt))
+    print("case: 256^3 mixed increment 1", flush=True)
+    r1 = s.step(Opts(tol=W.tol))
+    assert r1.status == 0
+    rho_prev = s.field("rho").cpu().numpy()
+    print("case: 256^3 mixed increment 2", flush=True)
+    r2 = s.step(Opts(tol=W.tol))
+    assert r2.status == 0 and r2.newton_failed == 0
+    sig = s.field("sigma").cpu().numpy()
+    e = s.field("strain").cpu().numpy()
+    ep = s.field("epsp").cpu().numpy()
+    rho = s.field("rho").cpu().numpy()
+    s.close()
+    nE = np.linalg.norm(voigt_to_mandel(r2.E))
+    # mean strain is the macroscopic strain (to FP32 rounding of the field)
+    assert np.abs(e.mean(axis=1) - r2.E).max() < 1e-5 * nE
+    assert abs(r2.E[2] + 2 * W.d_eps) < 1e-15
+    # stress-free lateral faces
+    S = sig.mean(axis=1)
+    assert np.abs(S[[0, 1, 3, 4, 5]]).max() < 10 * W.tol * abs(S[2])
+    # nuclei are softer: their mean |s33| is below the matrix's
+    nuc = rho0 < 1e11
+    assert nuc.mean() > 0.04
+    assert np.abs(sig[2][nuc]).mean() < np.abs(sig[2][~nuc]).mean()
+    # local law at sampled voxels: e = S:sigma + epsp at convergence
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.choice(np.flatnonzero(nuc), 64, replace=False),
+                          rng.choice(np.flatnonzero(~nuc), 192, replace=False)])
+    _, Sv, m = voxel_material(q[:, idx], 168400.0, 121400.0, 75400.0)
+    sg = voigt_to_mandel(sig[:, idx]).T
+    resid = voigt_to_mandel(e[:, idx]).T - (np.einsum("mkl,ml->mk", Sv, sg) + voigt_to_mandel(ep[:, idx]).T)
+    print("256^3 sampled local residual / |E|:", np.abs(resid).max() / nE, flush=True)
+    assert np.abs(resid).max() < 100 * W.tol * nE
+    # density update at the sampled voxels from the converged stress
+    tauc = 5.0 + 0.5 * 47337.0 * 2.56e-10 * np.sqrt(rho_prev[idx])
+    _, gd = L.slip_rates(sg, m, tauc, 1e-3, 10.0)
+    want = rho_prev[idx] + W.dt * (8e7 * np.sqrt(rho_prev[idx]) - 10.0 * rho_prev[idx]) * np.abs(gd).sum(axis=1)
+    assert np.abs(rho[idx] / want - 1).max() < 1e-5
+
+
+def _problem(micro, precision, every, tol, increments=3):
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    from paper_1509_04953_amd.adjoint import CurveProblem
+    q, rho = micro
+    s = Solver(W.shape, precision)
+    opts = Opts(tol=tol, max_iter=5000)
+    return CurveProblem(s, Material(), q, rho, Load(dt=W.dt), increments, opts, opts, every)
+
+
+def _grad(p, theta, target):
+    import torch
+    from paper_1509_04953_amd.adjoint import StressStrainCurve, curve_loss
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    c = StressStrainCurve.apply(th, p)
+    L_ = curve_loss(c, torch.tensor(target, dtype=torch.float64))
+    L_.backward()
+    return c.detach().numpy(), th.grad.numpy().copy()
+
+
+def test_256_adjoint_checkpointed(require_gpu, micro):
+    """Three increments, checkpoints every 2: the FP64 adjoint gradient
+    against central differences of the GPU forward (relative 1e-5), the
+    schedule every increment bit-identical, and the mixed adjoint within
+    1e-3 of the FP64 gradient."""
+    from paper_1509_04953_amd.adjoint import curve
+    th0 = np.array([5.0, 8.0e7, 10.0, 10.0])
+    p = _problem(micro, "fp64", 2, 1e-12)
+    target = curve(p, th0 * np.array([1.05, 0.95, 1.05, 0.95]))
+    print("case: 256^3 fp64 adjoint, checkpoints every 2", flush=True)
+    c, g = _grad(p, th0, target)
+    fd = np.zeros(4)
+    for k in range(4):
+        h = 1e-5 * abs(th0[k])
+        tp, tm = th0.copy(), th0.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd[k] = (np.mean((curve(p, tp) - target) ** 2) - np.mean((curve(p, tm) - target) ** 2)) / (2 * h)
+    print("adjoint", g, "\nfd     ", fd, flush=True)
+    assert (np.abs(g - fd) / np.abs(fd)).max() < 1e-5
+    p.solver.close()
+    p1 = _problem(micro, "fp64", 1, 1e-12)
+    _, g1 = _grad(p1, th0, target)
+    assert np.array_equal(g, g1)
+    p1.solver.close()
+    print("case: 256^3 mixed adjoint", flush=True)
+    pm = _problem(micro, "mixed", 2, 1e-6)
+    _, gm = _grad(pm, th0, target)
+    print("mixed adjoint", gm, flush=True)
+    assert (np.abs(gm - g) / np.abs(g)).max() < 1e-3
+    pm.solver.close()
