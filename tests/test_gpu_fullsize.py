@@ -195,3 +195,43 @@ def test_mixed_vs_fp64_128(require_gpu):
     assert errs["curve"] < 1e-5 and errs["strain"] < 1e-5
     assert errs["sigma"] < 5e-5
     assert errs["epsp"] < 1e-4 and errs["rho"] < 1e-4
+
+
+def test_64cube_fifty_increments_properties(require_gpu):
+    """64^3, 100 grains, 50 increments to 10 % strain (the whole loading
+    path of that configuration; the oracle's first three are compared in
+    test_curve_64cube_matches_golden): at the end, the mean strain, the
+    stress-free lateral faces, the local law and the density update at
+    sampled voxels, and a hardening curve."""
+    from paper_1509_04953_amd import Opts
+    w = synth.workload("cu64")
+    s, q, rho0 = make(w, "fp64")
+    curve = []
+    for inc in range(50):
+        if inc == 49:
+            rho_prev = s.field("rho").cpu().numpy()
+        r = s.step(Opts(tol=w.tol))
+        assert r.status == 0, inc
+        curve.append(r.Sigma[2])
+    print(f"case: 64^3 after 50 increments, <s33> {curve[-1]:.3f} MPa", flush=True)
+    assert abs(r.E[2] + 50 * w.d_eps) < 1e-12
+    c = -np.array(curve)
+    assert np.all(np.diff(c[10:]) > 0)          # compression hardens
+    sig = s.field("sigma").cpu().numpy()
+    e = s.field("strain").cpu().numpy()
+    ep = s.field("epsp").cpu().numpy()
+    rho = s.field("rho").cpu().numpy()
+    nE = np.linalg.norm(voigt_to_mandel(r.E))
+    assert np.abs(e.mean(axis=1) - r.E).max() < 1e-13
+    S = sig.mean(axis=1)
+    assert np.abs(S[[0, 1, 3, 4, 5]]).max() < 10 * w.tol * abs(S[2])
+    rng = np.random.default_rng(1)
+    idx = rng.choice(w.voxels, 256, replace=False)
+    _, Sv, m = voxel_material(q[:, idx], 168400.0, 121400.0, 75400.0)
+    sg = voigt_to_mandel(sig[:, idx]).T
+    resid = voigt_to_mandel(e[:, idx]).T - (np.einsum("mkl,ml->mk", Sv, sg) + voigt_to_mandel(ep[:, idx]).T)
+    assert np.abs(resid).max() < 50 * w.tol * nE
+    tauc = 5.0 + 0.5 * 47337.0 * 2.56e-10 * np.sqrt(rho_prev[idx])
+    _, gd = L.slip_rates(sg, m, tauc, 1e-3, 10.0)
+    want = rho_prev[idx] + w.dt * (8e7 * np.sqrt(rho_prev[idx]) - 10.0 * rho_prev[idx]) * np.abs(gd).sum(axis=1)
+    assert np.abs(rho[idx] - want).max() < 1e-12 * want.max()
