@@ -79,3 +79,35 @@ def test_checkpoint_schedule_is_exact(require_gpu):
     _, _, g1 = adjoint_grad(p1, th0, tgt)
     _, _, g3 = adjoint_grad(p3, th0, tgt)
     assert np.array_equal(g1, g3), (g1, g3)
+
+
+def test_adjoint_128_forty_increments(require_gpu):
+    """The adjoint configuration: 128^3, 300 grains, 40 increments, loss
+    against the curve of the perturbed parameters theta0 * (1.05, 0.95,
+    1.05, 0.95), default checkpoints (every ceil(sqrt 40) = 7): the adjoint
+    gradient against central differences of the GPU forward (FP64)."""
+    import torch
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    from paper_1509_04953_amd.adjoint import CurveProblem, curve
+    w = synth.workload("cu128adj")
+    q, rho, _ = synth.make_microstructure(w)
+    s = Solver(w.shape, "fp64")
+    opts = Opts(tol=1e-12, max_iter=5000)
+    p = CurveProblem(s, Material(), q.reshape(4, -1), rho.reshape(-1), Load(dt=w.dt), w.increments,
+                     opts, opts, 0)
+    th0 = Material().theta()
+    print("case: adjoint 128^3, 40 increments: target", flush=True)
+    tgt = curve(p, th0 * np.array([1.05, 0.95, 1.05, 0.95]))
+    print("case: adjoint 128^3, 40 increments: gradient", flush=True)
+    _, L, g = adjoint_grad(p, th0, tgt)
+    fd = np.zeros(4)
+    for k in range(4):
+        print(f"case: adjoint 128^3 finite difference {k}", flush=True)
+        h = 1e-5 * abs(th0[k])
+        tp, tm = th0.copy(), th0.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd[k] = (np.mean((curve(p, tp) - tgt) ** 2) - np.mean((curve(p, tm) - tgt) ** 2)) / (2 * h)
+    print("adjoint", g, "\nfd     ", fd, flush=True)
+    assert (np.abs(g - fd) / np.abs(fd)).max() < 1e-5
+    s.close()
