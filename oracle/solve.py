@@ -40,6 +40,7 @@ from .crystal import voxel_material
 from . import drx as DX
 from . import ma_roters as MR
 from . import pf as PF
+from . import rotation as ROT
 from .gnd import gnd_rates, next_leff
 from .green import gamma_field, green_apply
 from .tensors import (isotropic_c4, mandel_to_voigt, voigt_to_mandel, c4_to_mandel)
@@ -99,6 +100,7 @@ class Oracle:
         self.C, self.S, self.m = voxel_material(quat, C11, C12, C44)
         self.gnd = None
         self.mr = None
+        self.rot = False
         lam0, mu0 = c0 if c0 is not None else default_c0(C11, C12, C44)
         self.c0 = (lam0, mu0)
         self.C0_4 = isotropic_c4(lam0, mu0)
@@ -163,6 +165,11 @@ class Oracle:
         G["ret"] = np.where(soft[None], self.drx.s_soften * G["ret"], G["ret"])
         G["grains"] = new
         return int(changed.sum()), int(soft.sum())
+
+    def enable_rotation(self):
+        """Rotate the lattice by its spin (oracle.rotation) after every
+        increment from now on."""
+        self.rot = True
 
     def enable_mr(self, law=None):
         """Use the paper's own flow rule and SSD evolution (Sec. 2.2, Eq. 3-6;
@@ -270,6 +277,11 @@ class Oracle:
             G["rs"] = G["rs"] + load.dt * rs
             G["ret"] = G["ret"] + load.dt * ret
             G["leff"] = next_leff(G["leff"], E, G["xi"])
+        if self.rot:
+            # lattice rotation from the increment's slip rates (oracle.rotation),
+            # after the GND update, which uses the orientation they acted in
+            self.quat = ROT.rotate(self.quat, gdot, load.dt)
+            self.C, self.S, self.m = voxel_material(self.quat, *self.elastic)
         self.t += load.dt
         rep = dict(iters=iters, converged=converged, err_c=err_c, err_bc=err_bc,
                    Sigma=mandel_to_voigt(sig.mean(axis=0)), E=mandel_to_voigt(E),
@@ -285,6 +297,8 @@ class Oracle:
             return mandel_to_voigt(a.T)
         if name == "rho":
             return self.rho.copy()
+        if name == "quat":
+            return self.quat.copy()
         if name == "kappa":
             return self.kappa.copy()
         if name == "grain":
