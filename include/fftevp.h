@@ -66,7 +66,8 @@ typedef enum {
   FFTEVP_FIELD_RHO_GNDET = 8,   /* edge GND density per system, 12 comps, m^-2    */
   FFTEVP_FIELD_RHO_SSD = 9,     /* SSD density per system (paper's law), 12 comps */
   FFTEVP_FIELD_KAPPA = 10,      /* DRX nucleation strength, m^-2                  */
-  FFTEVP_FIELD_GRAIN = 11       /* grain ids (as doubles; nuclei negative)        */
+  FFTEVP_FIELD_GRAIN = 11,      /* grain ids (as doubles; nuclei negative)        */
+  FFTEVP_FIELD_QUAT = 12        /* orientation quaternions (w,x,y,z), 4 comps      */
 } fftevp_field;
 
 typedef struct fftevp_ctx fftevp_ctx;
@@ -229,6 +230,16 @@ fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double*
  * not change, so the stress needs no re-solve here. */
 fftevp_status fftevp_drx_nucleate(fftevp_ctx* ctx, const double* u_dev, long long* n_nuclei);
 
+/* Lattice rotation (reading of the orientation change of Sec. 2.5; the
+ * paper gives no equation): on = 1 turns, after every committed increment
+ * (after the GND update), each voxel's lattice by exp(dt Omega_e) with
+ * Omega_e = -sum_a gdot_a skew(d_a (x) n_a), the increment's slip rates and
+ * the sample-frame unit slip direction d_a and plane normal n_a; the imposed
+ * spin is zero and the local spin of the spectral solution is not included.
+ * Orientations then enter snapshots; the adjoint is unavailable (EINVAL).
+ * on = 0 (default) keeps them fixed. EINVAL unless on is 0 or 1. */
+fftevp_status fftevp_set_rotation(fftevp_ctx* ctx, int on);
+
 /* One strain increment: the fixed-point solve, then the explicit update of
  * plastic strain and density at the converged stress (Eq. 1 first-order
  * update; hardening law above). Returns OK, NOT_CONVERGED (max_iter reached:
@@ -271,7 +282,7 @@ fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
 
 /* Kernel timing (diagnostics). Bit k of class_mask brackets every launch of
  * kernel class k with HIP events on the context's stream: 0 local solve +
- * x-FFTs, 1 (unused), 2 forward y-FFT + first reduction stage, 3 z-FFT +
+ * x-FFTs, 1 lattice rotation, 2 forward y-FFT + first reduction stage, 3 z-FFT +
  * Green operator + stop test, 4 inverse y-FFT, 5 end-of-increment update,
  * 6 adjoint set-up and reverse update, 7 GND update. Durations of launches
  * that did work (not those skipped after convergence) are summed per class.

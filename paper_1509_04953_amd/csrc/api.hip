@@ -74,6 +74,7 @@ struct fftevp_ctx {
   bool gnd_on = false;
   int law = 0;          // 0: power law (hardening above), 1: the paper's law
   bool drx_on = false;
+  bool rot_on = false;  // lattice rotation after each increment
   fftevp_drx drx{};
   fftevp_mr mr{};
   MrConst mrc{};
@@ -520,7 +521,7 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     sa.k1 = ctx->flow.k1;
     sa.k2 = ctx->flow.k2;
     sa.m = m;
-    sa.gd = ctx->gnd_on ? (T*)ctx->b.gd : nullptr;
+    sa.gd = (ctx->gnd_on || ctx->rot_on) ? (T*)ctx->b.gd : nullptr;
     if (ctx->law == 1) {
       sa.ssd = (T*)ctx->b.ssd;
       sa.sysp = (const T*)ctx->b.sysp;
@@ -556,6 +557,11 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
       }
       ctx->leff *= 1.0 + std::sqrt(2.0 / 3.0 * ee) / ctx->xi;
     }
+    // lattice rotation from the same slip rates, after the GND update, which
+    // uses the orientation they acted in
+    if (ctx->rot_on)
+      HIPCHK(timed(ctx, 1, -1, [&] { return launch_rotate<T>((T*)ctx->b.quat, (const T*)ctx->b.gd, ctx->V, dt,
+                                                              ctx->stream); }));
     // the next increment's frozen parameters of the paper's law
     if (ctx->law == 1) HIPCHK(mr_params(ctx));
     HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -585,7 +591,7 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
   return ret;
 }
 
-size_t snap_layout(const fftevp_ctx* c, size_t off[8]) {
+size_t snap_layout(const fftevp_ctx* c, size_t off[9]) {
   const size_t ts = c->tsize, V = c->V;
   size_t o = kHeader * sizeof(double);
   off[0] = o;  // epsp
@@ -605,6 +611,8 @@ size_t snap_layout(const fftevp_ctx* c, size_t off[8]) {
   if (c->law == 1) o += 12 * V * ts;
   off[7] = o;  // DRX: nucleation strength [V] then grain ids [V] (int32)
   if (c->drx_on) o += V * ts + ((V * sizeof(int) + 255) & ~(size_t)255);
+  off[8] = o;  // orientations when the lattice rotates, [4][V]
+  if (c->rot_on) o += 4 * V * ts;
   return o;
 }
 
@@ -633,7 +641,7 @@ fftevp_status adjoint_impl(fftevp_ctx* ctx, const fftevp_opts& o, const void* be
   if (st != FFTEVP_OK) return st;
   if ((st = check_snapshot(ctx, after)) != FFTEVP_OK) return st;
   const size_t V = ctx->V, ts = sizeof(T);
-  size_t off[8];
+  size_t off[9];
   snap_layout(ctx, off);
   if (!ctx->b.a_eta) HIPCHK(hipMalloc(&ctx->b.a_eta, 6 * V * ts));
   AdjArgs<T> aa{};
@@ -1012,6 +1020,19 @@ fftevp_status fftevp_drx_grow(fftevp_ctx* ctx, fftevp_pf* pf, const fftevp_grow*
   return FFTEVP_OK;
 }
 
+fftevp_status fftevp_set_rotation(fftevp_ctx* ctx, int on) {
+  if (!ctx) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (on != 0 && on != 1) return fail(ctx, FFTEVP_EINVAL, "on must be 0 or 1");
+  if (on && !ctx->b.gd) {
+    if (hipMalloc(&ctx->b.gd, 12 * ctx->V * ctx->tsize) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
+    }
+  }
+  ctx->rot_on = on != 0;
+  return FFTEVP_OK;
+}
+
 fftevp_status fftevp_set_gnd(fftevp_ctx* ctx, const int* grain_dev, double l0, double xi) {
   if (!ctx || !grain_dev) return fail(ctx, FFTEVP_EINVAL, "null argument");
   if (!(l0 > 0.0 && std::isfinite(l0) && xi > 0.0 && std::isfinite(xi)))
@@ -1108,6 +1129,10 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
       if (!ctx->drx_on) return fail(ctx, FFTEVP_ESTATE, "DRX nucleation is not enabled (fftevp_set_drx)");
       e = exp(ctx->b.kappa, 1, 0);
       break;
+    case FFTEVP_FIELD_QUAT:
+      if (!ctx->have_micro) return fail(ctx, FFTEVP_ESTATE, "orientations come with fftevp_set_microstructure");
+      e = exp(ctx->b.quat, 4, 0);
+      break;
     case FFTEVP_FIELD_GRAIN:
       if (!ctx->gnd_on) return fail(ctx, FFTEVP_ESTATE, "grain ids come with fftevp_set_gnd");
       e = launch_export_int(ctx->b.grain, dst, V, ctx->stream);
@@ -1154,13 +1179,13 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
 
 size_t fftevp_state_bytes(const fftevp_ctx* ctx) {
   if (!ctx) return 0;
-  size_t off[8];
+  size_t off[9];
   return snap_layout(ctx, off);
 }
 
 fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   if (!ctx || !dst) return fail(ctx, FFTEVP_EINVAL, "null argument");
-  size_t off[8];
+  size_t off[9];
   snap_layout(ctx, off);
   const size_t ts = ctx->tsize, V = ctx->V;
   double hdr[kHeader] = {0};
@@ -1177,6 +1202,7 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   hdr[15] = ctx->leff;
   hdr[16] = ctx->law;
   hdr[17] = ctx->drx_on ? 1.0 : 0.0;
+  hdr[18] = ctx->rot_on ? 1.0 : 0.0;
   char* d = (char*)dst;
   HIPCHK(hipMemcpyAsync(d, hdr, sizeof hdr, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(d + off[0], ctx->b.epsp, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1196,13 +1222,15 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
     HIPCHK(hipMemcpyAsync(d + off[7], ctx->b.kappa, V * ts, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(d + off[7] + V * ts, ctx->b.grain, V * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
   }
+  if (ctx->rot_on)
+    HIPCHK(hipMemcpyAsync(d + off[8], ctx->b.quat, 4 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FFTEVP_OK;
 }
 
 fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   if (!ctx || !src) return fail(ctx, FFTEVP_EINVAL, "null argument");
-  size_t off[8];
+  size_t off[9];
   snap_layout(ctx, off);
   const size_t ts = ctx->tsize, V = ctx->V;
   double hdr[kHeader];
@@ -1211,7 +1239,7 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
       hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0) || hdr[16] != (double)ctx->law ||
-      hdr[17] != (ctx->drx_on ? 1.0 : 0.0))
+      hdr[17] != (ctx->drx_on ? 1.0 : 0.0) || hdr[18] != (ctx->rot_on ? 1.0 : 0.0))
     return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
   HIPCHK(hipMemcpyAsync(ctx->b.epsp, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.rho, s + off[1], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1229,6 +1257,8 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
     HIPCHK(hipMemcpyAsync(ctx->b.kappa, s + off[7], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->b.grain, s + off[7] + V * ts, V * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream));
   }
+  if (ctx->rot_on)
+    HIPCHK(hipMemcpyAsync(ctx->b.quat, s + off[8], 4 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   if (ctx->law == 1) {
     HIPCHK(hipMemcpyAsync(ctx->b.ssd, s + off[6], 12 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(mr_params(ctx));
@@ -1275,6 +1305,7 @@ fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(g[k])) return fail(ctx, FFTEVP_EINVAL, "non-finite dL/dSigma");
   if (ctx->law != 0) return fail(ctx, FFTEVP_EINVAL, "the adjoint covers the power law only");
+  if (ctx->rot_on) return fail(ctx, FFTEVP_EINVAL, "the adjoint assumes fixed orientations");
   const fftevp_opts o = resolve_opts(ctx, opts);
   return ctx->prec == FFTEVP_FP64 ? adjoint_impl<double>(ctx, o, before, after, g, adj, dth)
                                   : adjoint_impl<float>(ctx, o, before, after, g, adj, dth);

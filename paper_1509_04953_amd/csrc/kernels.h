@@ -211,6 +211,9 @@ hipError_t launch_kappa(const double* u, T* kappa, size_t V, double kc, double q
                         double* out2, hipStream_t s);
 template <typename T>
 hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, hipStream_t s);
+// lattice rotation by minus the plastic spin of the slip rates gd [12][V] over dt
+template <typename T>
+hipError_t launch_rotate(T* quat, const T* gd, size_t V, double dt, hipStream_t s);
 // scale x total dislocation density (Eq. 11) of every voxel into out [V]
 template <typename T>
 hipError_t launch_rho_tot(const DrxArgs<T>& a, bool mr, double scale, double* out, hipStream_t s);

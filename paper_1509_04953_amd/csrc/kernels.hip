@@ -963,6 +963,52 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
   }
 }
 
+// Lattice rotation after an increment (reading of Sec. 2.5): the lattice spins
+// with minus the plastic spin, Omega_e = -sum_a gdot_a skew(d_a (x) n_a) (no
+// imposed spin), whose axial vector is -1/2 sum_a gdot_a R t_a with the unit
+// sense vector t = n x d = (integer n x integer d) / sqrt6; the orientation
+// turns by exp(dt Omega_e): q <- (cos(|th|/2), sin(|th|/2) th/|th|) q with
+// th = dt times that axial vector, renormalised, w >= 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rotate(T* __restrict__ quat, const T* __restrict__ gd, size_t V,
+                                                double dt) {
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
+    const double q0 = quat[g], q1 = quat[V + g], q2 = quat[2 * V + g], q3 = quat[3 * V + g];
+    double u[3] = {0.0, 0.0, 0.0};  // sum_a gdot_a (integer n x d), crystal frame
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      const double r = gd[(size_t)a * V + g];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) u[j] += r * (double)kT[a][j];
+    }
+    double R[9];
+    quat_rot<double>(q0, q1, q2, q3, R);
+    const double c = -0.5 * dt * 0.40824829046386301637;  // -dt / (2 sqrt6)
+    double th[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) th[i] = c * (R[3 * i] * u[0] + R[3 * i + 1] * u[1] + R[3 * i + 2] * u[2]);
+    const double ang = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+    double a0 = 1.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (ang > 0.0) {
+      const double sh = sin(0.5 * ang) / ang;
+      a0 = cos(0.5 * ang);
+      a1 = sh * th[0];
+      a2 = sh * th[1];
+      a3 = sh * th[2];
+    }
+    // Hamilton product (a0, a) (q0, q)
+    double w = a0 * q0 - a1 * q1 - a2 * q2 - a3 * q3;
+    double x = a0 * q1 + a1 * q0 + a2 * q3 - a3 * q2;
+    double y = a0 * q2 - a1 * q3 + a2 * q0 + a3 * q1;
+    double z = a0 * q3 + a1 * q2 - a2 * q1 + a3 * q0;
+    const double inv = (w < 0.0 ? -1.0 : 1.0) / sqrt(w * w + x * x + y * y + z * z);
+    quat[g] = (T)(w * inv);
+    quat[V + g] = (T)(x * inv);
+    quat[2 * V + g] = (T)(y * inv);
+    quat[3 * V + g] = (T)(z * inv);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the paper's dislocation-based law (Sec. 2.2, Eq. 3-6)
 // ---------------------------------------------------------------------------
@@ -1615,6 +1661,12 @@ hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, h
 }
 
 template <typename T>
+hipError_t launch_rotate(T* quat, const T* gd, size_t V, double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_rotate<T>, dim3(grid_for(V)), dim3(256), 0, s, quat, gd, V, dt);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_rho_tot(const DrxArgs<T>& a, bool mr, double scale, double* out, hipStream_t s) {
   if (mr) hipLaunchKernelGGL((k_rho_tot<T, true>), dim3(grid_for(a.V)), dim3(256), 0, s, a, scale, out);
   else hipLaunchKernelGGL((k_rho_tot<T, false>), dim3(grid_for(a.V)), dim3(256), 0, s, a, scale, out);
@@ -1688,6 +1740,7 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
                                       hipStream_t);                                           \
   template hipError_t launch_drx<T>(const DrxArgs<T>&, bool, int, double*, hipStream_t);      \
   template hipError_t launch_rho_tot<T>(const DrxArgs<T>&, bool, double, double*, hipStream_t); \
+  template hipError_t launch_rotate<T>(T*, const T*, size_t, double, hipStream_t);             \
   template hipError_t launch_sweep<T>(const DrxArgs<T>&, int, double*, hipStream_t);          \
   template hipError_t launch_mr_params<T>(const T*, const T*, const T*, T*, size_t, const MrConst&, \
                                           hipStream_t);                                       \

@@ -19,11 +19,11 @@ _lib = None
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENONFINITE, ELOCAL, ESTATE = 0, 1, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
 FIELDS = {"sigma": 0, "strain": 1, "epsp": 2, "rho": 3, "sigma_iter": 4, "strain_iter": 5, "gdot": 6,
-          "rho_gnds": 7, "rho_gndet": 8, "rho_ssd": 9, "kappa": 10, "grain": 11}
+          "rho_gnds": 7, "rho_gndet": 8, "rho_ssd": 9, "kappa": 10, "grain": 11, "quat": 12}
 NPROF = 8
-PROF_NAMES = ("local", "unused", "yfwd", "zgamma", "yinv", "state", "adjoint", "gnd")
+PROF_NAMES = ("local", "rotate", "yfwd", "zgamma", "yinv", "state", "adjoint", "gnd")
 NCOMP = {"sigma": 6, "strain": 6, "epsp": 6, "rho": 1, "sigma_iter": 6, "strain_iter": 6, "gdot": 12,
-         "rho_gnds": 12, "rho_gndet": 12, "rho_ssd": 12, "kappa": 1, "grain": 1}
+         "rho_gnds": 12, "rho_gndet": 12, "rho_ssd": 12, "kappa": 1, "grain": 1, "quat": 4}
 
 
 class Cubic(C.Structure):
@@ -82,6 +82,7 @@ def library():
         "fftevp_set_gnd": (I, [P, P, C.c_double, C.c_double]),
         "fftevp_set_law": (I, [P, I, C.POINTER(MRC)]),
         "fftevp_set_drx": (I, [P, C.POINTER(DrxC), P]),
+        "fftevp_set_rotation": (I, [P, I]),
         "fftevp_drx_nucleate": (I, [P, P, C.POINTER(C.c_longlong)]),
         "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_get_field": (I, [P, I, P]),
@@ -276,6 +277,10 @@ class Solver:
         self._check(self.lib.fftevp_drx_grow(self.h, pf.h, C.byref(GrowC(zeta, omega_gb, dx)), int(nsteps),
                                              C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
+
+    def set_rotation(self, on: bool = True):
+        """Turn the lattice by its spin after every increment (include/fftevp.h)."""
+        self._check(self.lib.fftevp_set_rotation(self.h, int(bool(on))))
 
     def drx_cycle(self, pf: "PhaseField", u, pf_steps: int, opts: Opts | None = None, zeta: float = 0.25,
                   omega_gb: float = 0.625, dx: float = 10.7e-6):
