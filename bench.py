@@ -152,6 +152,29 @@ def run_gnd(w, quat, rho, grains, precision, increments=4):
             "l_eff_m": r.l_eff}
 
 
+def run_rotation(w, quat, rho, precision, increments=4):
+    """Lattice rotation after each increment (k_rotate): HIP-event time per
+    increment and the rate of its algorithmic bytes (slip rates 12 words and
+    orientation 4 words read, orientation 4 words written per voxel)."""
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load(dt=w.dt))
+    s.set_rotation(True)
+    s.set_profiling(True, classes=("rotate",))
+    s.profile(reset=True)
+    for _ in range(increments):
+        s.step(Opts(tol=w.tol, max_iter=2000))
+    ms, n = s.profile(reset=True)["rotate"]
+    s.close()
+    word = 8 if precision == "fp64" else 4
+    nbytes = 20 * w.voxels * word
+    avg = ms / max(n, 1)
+    return {"precision": precision, "ms_per_increment": avg, "increments": n,
+            "GBps": nbytes / (avg * 1e-3) / 1e9, "frac_hbm": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def run_mr(w, quat, rho, precision, steps=3, warmup=1):
     """The paper's own flow rule and SSD evolution (Sec. 2.2, Eq. 3-6) on the
     same workload (initial SSD density 2.5e12 m^-2 per voxel scaled by the
@@ -509,6 +532,7 @@ def main():
         line["gnd"] = run_gnd(w, quat, rho, grains, precs[0])
     if not args.no_gnd:
         line["drx"] = run_drx(w, quat, rho, grains, precs[0])
+        line["rotation"] = run_rotation(w, quat, rho, precs[0])
     if not args.no_mr:
         line["paper_law"] = {p: run_mr(w, quat, rho, p) for p in precs}
     if not args.no_pf:
