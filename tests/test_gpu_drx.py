@@ -120,7 +120,8 @@ def test_drx_grow_matches_oracle(require_gpu, law, dx):
     if law == "paper":
         s.set_law(MaRoters())
         o.enable_mr(OMR.MaRoters())
-    kc = 3.0e12 if law == "power" else 6.0e12
+    # a characteristic density that nucleates a few dozen grains
+    kc = 1.0e13 if law == "power" else 6.0e12
     s.set_drx(u0, kc=kc)
     o.enable_drx(ODX.DRX(kc=kc), u0)
     pf = PhaseField(shape, K=6, threshold=1e-5)
