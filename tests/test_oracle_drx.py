@@ -4,6 +4,7 @@ propensity and the event rules."""
 import math
 
 import numpy as np
+import pytest
 
 from oracle import Oracle, Loading
 from oracle import drx as DX
@@ -72,3 +73,55 @@ def test_nucleation_events():
     assert np.allclose(G["rs"][:, hit], 0.9 * rs0[:, hit]) and np.allclose(G["ret"][:, ~hit], re0[:, ~hit])
     assert np.allclose(o.kappa[hit], 0.05 * 1.5e12 * (-np.log1p(-u1[hit])) ** (1 / 4.4))
     assert np.array_equal(o.kappa[~hit], kap0[~hit])
+
+
+def test_total_density_with_mobile_density_by_hand():
+    """Eq. 11 with the paper's law: one voxel, density 1e12 split equally over
+    the 12 systems, no GND: rho_F = 4 sqrt2 rho_a, rho_P = (4 + 2 sqrt7) rho_a
+    (the row sums of the interaction tables), rho_M^a = 0.026495477 rho_a at
+    473 K (see test_oracle_mr), so k = 12 (rho_a + rho_M^a) = 1.0264955e12.
+    A GND density adds its magnitude sqrt(screw^2 + edge^2) and raises the
+    mobile densities through the projections."""
+    from oracle import ma_roters as MR
+    law = MR.MaRoters()
+    ssd = np.full((1, 12), 1e12 / 12)
+    zero = np.zeros((12, 1))
+    k = DX.total_density(np.array([1e12]), zero, zero, law, ssd)
+    assert abs(k[0] - 1.0264954774514e12) < 1e-9 * 1e12
+    gs, ge = zero.copy(), zero.copy()
+    gs[0], ge[0] = 3e11, 4e11
+    k2 = DX.total_density(np.array([1e12]), gs, ge, law, ssd)
+    assert k2[0] > k[0] + 5e11
+
+
+@pytest.mark.parametrize("factor, grows", [(1.6, True), (0.6, False)])
+def test_growth_stored_energy_against_capillarity(factor, grows):
+    """drx_grow converts the total density to the stored energy of Eq. 14,
+    rho zeta mu b^2 (J/m^3), in the phase field's energy unit. In SI a
+    recrystallised sphere of radius R in a deformed matrix grows when that
+    energy exceeds the capillary pressure 2 omega / R and shrinks below it.
+    Coarse sphere of radius 6 voxels (12 PF cells of dx = 1 um), omega =
+    0.625 J/m^2, zeta = 0.25: the critical density is 2 omega / (12 dx zeta mu
+    b^2) = 1.0417e5 / 7.7558e-10 = 1.3431e14 m^-2; at 1.6x it grows, at 0.6x
+    it shrinks."""
+    n = 24
+    shape = (n, n, n)
+    V = n ** 3
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r2 = (x + 0.5 - n / 2) ** 2 + (y + 0.5 - n / 2) ** 2 + (z + 0.5 - n / 2) ** 2
+    inside = (r2 <= 36.0).reshape(-1)
+    rho_c = 2 * 0.625 / (12 * 1e-6) / (0.25 * 47337e6 * 2.56e-10 ** 2)
+    assert abs(rho_c / 1.34306e14 - 1) < 1e-4
+    quat = np.tile(np.array([1.0, 0, 0, 0])[:, None], (1, V))
+    o = Oracle(shape, quat, np.full(V, factor * rho_c))
+    o.enable_gnd(np.where(inside, -1, 0), 21.4e-6, 200.0)
+    o.enable_drx(DX.DRX(), np.full(V, 0.5))
+    before = o.field("grain").copy()
+    changed, rex = o.drx_grow(400, zeta=0.25, omega_gb=0.625, dx=1e-6, K=2, threshold=1e-5)
+    after = o.field("grain")
+    gained = int(((before == 0) & (after == -1)).sum())
+    lost = int(((before == -1) & (after == 0)).sum())
+    if grows:
+        assert gained > 50 and lost == 0, (gained, lost)
+    else:
+        assert lost > 50 and gained == 0, (gained, lost)
