@@ -78,6 +78,13 @@ class StressStrainCurve(torch.autograd.Function):
     def backward(ctx, grad):
         p, every, ckpts = ctx.p, ctx.every, ctx.ckpts
         s = p.solver
+        # the solver may have run other parameters since this forward (several
+        # curves in one loss, a line search): the recomputed segments and the
+        # adjoint solves must use this forward's parameters, microstructure
+        # and loading (snapshots hold the state, not these)
+        s.set_material(_material(p.material, ctx.theta))
+        s.set_microstructure(p.quat, p.rho)
+        s.set_loading(p.load)
         g = grad.detach().cpu().numpy().astype(np.float64)
         T = p.increments
         adj = torch.zeros(s.adjoint_bytes(), dtype=torch.uint8, device="cuda")

@@ -13,6 +13,11 @@ Both solve each increment to a stop tolerance of 1e-13.
 * curve_64cube.json: the 64^3, 100-grain, log-normal-density polycrystal
   over its first 3 increments at the workload's stop tolerance 1e-6, with
   the iteration counts and sampled fields (slow: about 10 minutes).
+* curve_128cube.json: the 128^3, 500-grain, log-normal-density benchmark
+  polycrystal over its first increment at the workload's stop tolerance
+  1e-6: iteration count, mean stress and strain, and the stress, strain,
+  plastic strain and density at 256 sampled voxels (slow: about 30 minutes
+  and 10 GB of memory).
 """
 import json
 import os
@@ -67,6 +72,22 @@ def curve64():
             "rho_sample": o.field("rho")[idx].tolist()}
 
 
+def curve128():
+    from oracle import Oracle
+    w = synth.workload("cu128")
+    q, rho, _ = synth.make_microstructure(w)
+    o = Oracle(w.shape, q.reshape(4, -1), rho.reshape(-1))
+    r = o.increment(Loading(), tol=w.tol, max_iter=2000)
+    idx = np.random.default_rng(128).choice(w.voxels, 256, replace=False)
+    return {"workload": "cu128", "increments": 1, "curve": [r["Sigma"][2]], "Sigma": [list(r["Sigma"])],
+            "iters": [r["iters"]], "E": [list(r["E"])], "tol": w.tol, "err_c": r["err_c"],
+            "err_bc": r["err_bc"], "sample_index": idx.tolist(),
+            "sigma_sample": o.field("sigma")[:, idx].tolist(),
+            "strain_sample": o.field("strain")[:, idx].tolist(),
+            "epsp_sample": o.field("epsp")[:, idx].tolist(),
+            "rho_sample": o.field("rho")[idx].tolist()}
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["adjoint", "curve16"]
     if "adjoint" in which:
@@ -75,6 +96,9 @@ if __name__ == "__main__":
     if "curve16" in which:
         with open(os.path.join(HERE, "curve_16cube.json"), "w") as fh:
             json.dump(curve16(), fh, indent=1)
+    if "curve128" in which:
+        with open(os.path.join(HERE, "curve_128cube.json"), "w") as fh:
+            json.dump(curve128(), fh, indent=1)
     if "curve64" in which:
         with open(os.path.join(HERE, "curve_64cube.json"), "w") as fh:
             json.dump(curve64(), fh, indent=1)

@@ -77,6 +77,36 @@ def test_error_paths(require_gpu):
     assert abs(r.E[2] + 2e-3) < 1e-15
 
 
+def test_local_and_nonfinite_error_paths(require_gpu):
+    """ELOCAL: with one Newton iteration per voxel the increment still
+    converges (the local solves are inexact but the fixed point is the same)
+    and is committed, flagged ELOCAL with the number of voxels whose solve
+    stopped at the limit. ENONFINITE: a loading so large that the flow rule
+    overflows makes the residual non-finite; the stop test ends the
+    iteration, nothing is committed and the next, sane increment runs from
+    the unchanged state."""
+    from paper_1509_04953_amd import Load, Opts, ELOCAL, ENONFINITE, FftevpError
+    print("case: ELOCAL 16^3 fp64", flush=True)
+    s, quat, rho = solver()
+    r = s.step(Opts(tol=1e-6, newton_max=1, max_iter=3000))
+    assert r.status == ELOCAL and r.newton_failed > 0, (r.status, r.newton_failed)
+    assert abs(r.E[2] + 2e-3) < 1e-15
+    assert np.abs(s.field("epsp").cpu().numpy()).max() > 0.0    # committed
+    s.close()
+    print("case: ENONFINITE 16^3 fp64", flush=True)
+    s, quat, rho = solver()
+    s.set_loading(Load(Edot=(0, 0, -1e300, 0, 0, 0)))
+    with pytest.raises(FftevpError) as e:
+        s.step(Opts(tol=1e-6, max_iter=50))
+    assert e.value.status == ENONFINITE
+    assert np.array_equal(s.field("sigma").cpu().numpy(), np.zeros((6, 16 ** 3)))
+    assert np.array_equal(s.field("epsp").cpu().numpy(), np.zeros((6, 16 ** 3)))
+    s.set_loading(Load())
+    r = s.step(Opts(tol=1e-8))
+    assert r.status == 0 and abs(r.E[2] + 2e-3) < 1e-15
+    s.close()
+
+
 def test_snapshot_resume_is_bit_exact(require_gpu):
     from paper_1509_04953_amd import Opts
     print("case: snapshots", flush=True)

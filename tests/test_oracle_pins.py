@@ -504,3 +504,39 @@ def test_reference_medium_does_not_change_the_fixed_point(poly8):
         assert r["converged"]
         out.append(o.field("sigma"))
     assert np.abs(out[0] - out[1]).max() < 1e-8 * np.abs(out[0]).max()
+
+
+def test_global_quarter_turn_about_z_permutes_the_fields():
+    """P11: turning the whole polycrystal by 90 degrees about z (orientations
+    q -> r q, voxel (x, y) -> (n-1-y, x)) under compression along z with free
+    lateral faces (a loading the turn leaves unchanged) turns every field:
+    s'11 = s22, s'22 = s11, s'33 = s33, s'23 = s13, s'13 = -s23, s'12 = -s12
+    at the turned voxel."""
+    shape = (8, 8, 4)
+    g = [np.random.default_rng(s) for s in np.random.SeedSequence(31).spawn(4)]
+    grains = synth.voronoi_grains(shape, 4, g[0])
+    q = synth.random_quaternions(4, g[1])
+    quat = np.moveaxis(q[grains], -1, 0)                    # (4, z, y, x)
+    rho = synth.lognormal_rho(shape, 1e12, 0.3, g[2])       # (z, y, x)
+
+    def turn(f):          # field [..., z, y, x] -> turned grid
+        return np.flip(np.swapaxes(f, -1, -2), axis=-1)
+
+    r = q_axis_angle([0, 0, 1], np.pi / 2)
+    quat2 = turn(np.einsum("ij,j...->i...", np.array([q_mul(r, e) for e in np.eye(4)]).T, quat))
+    quat2 = np.where(quat2[0:1] < 0, -quat2, quat2)
+    o1 = Oracle(shape, quat.reshape(4, -1), rho.reshape(-1))
+    o2 = Oracle(shape, quat2.reshape(4, -1), turn(rho).reshape(-1))
+    for _ in range(2):
+        r1 = o1.increment(Loading(), tol=1e-12, max_iter=3000)
+        r2 = o2.increment(Loading(), tol=1e-12, max_iter=3000)
+    s1 = o1.field("sigma").reshape(6, 4, 8, 8)
+    s2 = o2.field("sigma").reshape(6, 4, 8, 8)
+    want = np.stack([s1[1], s1[0], s1[2], s1[4], -s1[3], -s1[5]])
+    scale = np.abs(s1).max()
+    assert np.abs(s2 - turn(want)).max() < 1e-9 * scale
+    e1 = o1.field("epsp").reshape(6, 4, 8, 8)
+    e2 = o2.field("epsp").reshape(6, 4, 8, 8)
+    wante = np.stack([e1[1], e1[0], e1[2], e1[4], -e1[3], -e1[5]])
+    assert np.abs(e2 - turn(wante)).max() < 1e-9 * np.abs(e1).max()
+    assert abs(r1["Sigma"][2] - r2["Sigma"][2]) < 1e-10 * abs(r1["Sigma"][2])
