@@ -247,6 +247,21 @@ fftevp_status fftevp_set_rotation(fftevp_ctx* ctx, int on);
  * some voxel Newton solves hit newton_max; state committed). out may be NULL. */
 fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_report* out);
 
+/* fftevp_step without any allocation, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc). Same
+ * increment, same kernels and bit-identical results as fftevp_step; the
+ * increment's scratch (per-block partial sums, first-stage sums, control
+ * block, reduction pair: about 6.3 MB) lives in a static device array of
+ * the library instead of the context, one copy per device, held until the
+ * process ends. The context must have been created (fftevp_create allocates
+ * its fields as before); the call itself allocates nothing, device or
+ * host. Limits: at most 2^24 voxels (EINVAL otherwise, nothing changed).
+ * Calls that overlap on one device (two host threads, or two contexts on
+ * different streams of the same device) share that array and race: the
+ * caller serialises them. Kernel timing (fftevp_set_profiling) is not
+ * recorded for this call. Returns as fftevp_step. */
+fftevp_status fftevp_step_noalloc(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_report* out);
+
 /* Copy a field (fftevp_field) into dst_dev (device, FP64, [ncomp][V]).
  * FFTEVP_FIELD_GDOT: the flow rule (Eq. 2 with the power law above) evaluated
  * at the committed stress and the current density, one rate per slip system

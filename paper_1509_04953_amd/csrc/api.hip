@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1084,6 +1085,97 @@ fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_repor
     return fail(ctx, FFTEVP_EINVAL, "bad options");
   const fftevp_opts o = resolve_opts(ctx, opts);
   return ctx->prec == FFTEVP_FP64 ? step_impl<double>(ctx, o, out) : step_impl<float>(ctx, o, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// fftevp_step_noalloc: the scratch of an increment in a static device array
+// ---------------------------------------------------------------------------
+// The increment's scratch is small next to its fields: the local kernel's
+// per-block partial sums (NPART per block of 256 voxels, or of 512 when
+// n0 = 512), the first-stage sums of the forward y pass (NPART x <= 64), the
+// control block, and the end-of-increment reduction pair. For grids of at
+// most 2^24 voxels it fits the array below; each device that runs the entry
+// point holds its own copy until the process ends.
+namespace {
+constexpr size_t kNaMaxVoxels = size_t(1) << 24;
+constexpr size_t kNaPartial = kNaMaxVoxels / 256 * NPART;  // doubles (>= 1024 x 4)
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaOffStage1 = round256(kNaPartial * sizeof(double));
+constexpr size_t kNaOffCtl = kNaOffStage1 + round256(NPART * 64 * sizeof(double));
+constexpr size_t kNaOffRed2 = kNaOffCtl + round256(sizeof(Ctl));
+constexpr size_t kNaBytes = kNaOffRed2 + round256(8 * sizeof(double));
+static_assert(kNaPartial >= 1024 * 4, "the end-of-increment reduction needs 4096 partials");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+std::mutex na_mu;
+void* na_base[kNaMaxDevices] = {};
+
+// Device address of this device's copy of the scratch array, looked up once
+// per device with that device current (host code never uses the array's
+// name as an address).
+hipError_t na_scratch(hipStream_t stream, void** out) {
+  int dev = 0, cur = 0;
+  hipError_t e = hipStreamGetDevice(stream, &dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(na_mu);
+  if (!na_base[dev]) {
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    na_base[dev] = p;
+  }
+  *out = na_base[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+fftevp_status fftevp_step_noalloc(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_report* out) {
+  if (!ctx) return FFTEVP_EINVAL;
+  if (ctx->V > kNaMaxVoxels)
+    return fail(ctx, FFTEVP_EINVAL, "fftevp_step_noalloc: at most 2^24 voxels (use fftevp_step)");
+  const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 4);
+  if (np > kNaPartial) return fail(ctx, FFTEVP_EINVAL, "fftevp_step_noalloc: scratch too small for this grid");
+  void* base = nullptr;
+  const hipError_t e = na_scratch(ctx->stream, &base);
+  if (e != hipSuccess) return fail(ctx, FFTEVP_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+  unsigned char* b = static_cast<unsigned char*>(base);
+  double* const partial = ctx->partial;
+  double* const stage1 = ctx->stage1;
+  Ctl* const ctl = ctx->ctl;
+  double* const red2 = ctx->red2;
+  const unsigned prof = ctx->prof;
+  // Every scratch word is written before it is read within the increment
+  // (partials by the local kernel, first-stage sums by the forward y pass,
+  // the control block by a copy from the host, the reduction pair by its
+  // kernel), so nothing needs clearing. Kernel timing creates events, so it
+  // is off for this call.
+  ctx->partial = reinterpret_cast<double*>(b);
+  ctx->stage1 = reinterpret_cast<double*>(b + kNaOffStage1);
+  ctx->ctl = reinterpret_cast<Ctl*>(b + kNaOffCtl);
+  ctx->red2 = reinterpret_cast<double*>(b + kNaOffRed2);
+  ctx->prof = 0;
+  const fftevp_status st = fftevp_step(ctx, opts, out);
+  ctx->partial = partial;
+  ctx->stage1 = stage1;
+  ctx->ctl = ctl;
+  ctx->red2 = red2;
+  ctx->prof = prof;
+  return st;
 }
 
 fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {

@@ -85,6 +85,7 @@ def library():
         "fftevp_set_rotation": (I, [P, I]),
         "fftevp_drx_nucleate": (I, [P, P, C.POINTER(C.c_longlong)]),
         "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
+        "fftevp_step_noalloc": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_get_field": (I, [P, I, P]),
         "fftevp_state_bytes": (S, [P]),
         "fftevp_save_state": (I, [P, P]),
@@ -311,6 +312,15 @@ class Solver:
     def step(self, opts: Opts | None = None, allow=(OK, NOT_CONVERGED, ELOCAL)) -> Report:
         r = ReportC()
         st = self._check(self.lib.fftevp_step(self.h, C.byref(_opts(opts)), C.byref(r)), allow)
+        return Report(st, r.iters, r.newton_max_seen, r.newton_failed, r.err_c, r.err_bc,
+                      np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean, r.newton_mean,
+                      r.linesearch_mean, r.l_eff)
+
+    def step_noalloc(self, opts: Opts | None = None, allow=(OK, NOT_CONVERGED, ELOCAL)) -> Report:
+        """fftevp_step_noalloc: the same increment with its scratch in the
+        library's static device array (no allocation in the call)."""
+        r = ReportC()
+        st = self._check(self.lib.fftevp_step_noalloc(self.h, C.byref(_opts(opts)), C.byref(r)), allow)
         return Report(st, r.iters, r.newton_max_seen, r.newton_failed, r.err_c, r.err_bc,
                       np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean, r.newton_mean,
                       r.linesearch_mean, r.l_eff)
