@@ -242,8 +242,10 @@ def run_drx(w, quat, rho, grains, precision, tests=4):
 
 def run_coupled(w, quat, rho, grains, precision, cycles=3, pf_steps=20):
     """The coupled loop (Sec. 2.5) on the workload: per increment the
-    mechanical solve with GND tracking, the nucleation test, and pf_steps
-    phase-field steps on the 2:1 grid with the grain map written back. Host
+    mechanical solve with GND tracking, the nucleation test, pf_steps
+    phase-field steps on the 2:1 grid with the grain map written back, and
+    the stress redistribution (the increment's solve repeated with the
+    updated microstructure). Host
     wall time per phase (each phase ends with a synchronisation), stored
     energy at a PF spacing of 1 mm so that nuclei grow."""
     import torch
@@ -257,10 +259,11 @@ def run_coupled(w, quat, rho, grains, precision, cycles=3, pf_steps=20):
     s.set_drx(torch.rand(w.voxels, dtype=torch.float64, device="cuda", generator=gen), kc=4.0e12)
     pf = PhaseField(w.shape, K=6, threshold=1e-5, precision=precision)
     opts = Opts(tol=w.tol, max_iter=2000)
-    t = {"solve": 0.0, "nucleate": 0.0, "grow": 0.0}
+    t = {"solve": 0.0, "nucleate": 0.0, "grow": 0.0, "redistribute": 0.0}
     log = []
     for _ in range(cycles):
         u = torch.rand(w.voxels, dtype=torch.float64, device="cuda", generator=gen)
+        before = s.save_state()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = s.step(opts)
@@ -270,10 +273,14 @@ def run_coupled(w, quat, rho, grains, precision, cycles=3, pf_steps=20):
         ch, rex = s.drx_grow(pf, pf_steps, dx=1.0e-3)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        rr = s.redistribute(before, opts)
+        t4 = time.perf_counter()
         t["solve"] += t1 - t0
         t["nucleate"] += t2 - t1
         t["grow"] += t3 - t2
-        log.append({"iters": r.iters, "nuclei": n, "changed": ch, "recrystallised": rex})
+        t["redistribute"] += t4 - t3
+        log.append({"iters": r.iters, "nuclei": n, "changed": ch, "recrystallised": rex,
+                    "redistribution_iters": rr.iters, "s33": r.Sigma[2], "s33_redistributed": rr.Sigma[2]})
     pf.close()
     s.close()
     return {"precision": precision, "cycles": cycles, "pf_steps": pf_steps,

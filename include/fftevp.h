@@ -226,9 +226,31 @@ fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double*
  * its GND densities (Eq. 16; SSD densities and orientation unchanged) and
  * draws a new strength with s_nucl kc at u_dev (device, FP64 [V] in [0, 1),
  * checked first: EINVAL changes nothing). The number of nuclei goes to
- * *n_nuclei (may be NULL). With orientations inherited the elastic moduli do
- * not change, so the stress needs no re-solve here. */
+ * *n_nuclei (may be NULL). The stress is then out of balance with the
+ * softened nuclei (their slip resistances drop with the paper's law):
+ * fftevp_redistribute computes the new equilibrium. */
 fftevp_status fftevp_drx_nucleate(fftevp_ctx* ctx, const double* u_dev, long long* n_nuclei);
+
+/* Stress redistribution after the DRX microstructure update (Sec. 2.5: the
+ * equilibrium stress is computed again, with the pre-DRX strain rate
+ * prescribed, before further loading). Repeats the last increment's solve
+ * from the mechanical state stored in state_before_dev (a snapshot, from
+ * fftevp_save_state, taken just before that increment: its plastic strain,
+ * stress, compatible strain and mean strain), with the same loading (the
+ * same prescribed macroscopic strain increment over the same dt) and the
+ * current microstructure: densities, GND densities, grains and orientations
+ * as the increment, fftevp_drx_nucleate and fftevp_drx_grow left them, so
+ * the slip resistances of the softened points. Commits the new stress,
+ * compatible strain, mean strain and the plastic strain of the repeated
+ * increment (start value + dt times the rate at the new stress); densities,
+ * effective length, orientations and time are not advanced again. With the
+ * power law and a density that did not change the result is the committed
+ * state itself. Needs fftevp_set_drx (ESTATE). EINVAL if the snapshot does
+ * not belong to this context or is not from exactly one increment before
+ * the current time. NOT_CONVERGED / ENONFINITE change nothing; ELOCAL as for
+ * fftevp_step. out may be NULL. */
+fftevp_status fftevp_redistribute(fftevp_ctx* ctx, const void* state_before_dev, const fftevp_opts* opts,
+                                  fftevp_report* out);
 
 /* Lattice rotation (reading of the orientation change of Sec. 2.5; the
  * paper gives no equation): on = 1 turns, after every committed increment

@@ -18,10 +18,10 @@ TEST INFRASTRUCTURE ONLY.
   densities and orientation stay (Sec. 2.5); its kappa is redrawn with
   k_c' = s_nucl k_c from a fresh uniform number. All sites are tested on the
   state after the increment, then updated together.
-* Stress redistribution (Sec. 2.5) re-solves equilibrium with the pre-DRX
-  strain-rate field prescribed; with orientations inherited and the elastic
-  moduli unchanged that leaves the stress as it is, so no solve is needed
-  without the phase-field growth step (which is not part of this code).
+* Stress redistribution (Sec. 2.5): after the update the equilibrium stress is
+  computed again before further loading, with the pre-DRX strain rate
+  prescribed (Oracle.redistribute repeats the last increment's solve from its
+  start state with the updated slip resistances).
 """
 from __future__ import annotations
 

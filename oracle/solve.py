@@ -213,8 +213,35 @@ class Oracle:
         e = np.fft.ifftn(eh, axes=(1, 2, 3))
         return np.ascontiguousarray(e.real.reshape(6, -1).T)
 
+    # -- stress redistribution after the microstructure update -----------
+    def mechanical_state(self):
+        """Copy of the mechanical state (plastic strain, stress, compatible
+        strain, mean strain) that a stress redistribution restarts from."""
+        return dict(epsp=self.epsp.copy(), sigma=self.sigma.copy(), e=self.e.copy(), E=self.E.copy())
+
+    def redistribute(self, before, load: Loading, tol=1e-6, max_iter=1000):
+        """Stress redistribution (Sec. 2.5): after nucleation and growth have
+        changed the microstructure, the equilibrium stress is computed again
+        before further loading, with the strain rate of the last increment
+        prescribed. Reading: the last increment's solve is repeated from its
+        mechanical start state ``before`` (taken with mechanical_state() before
+        that increment) with the same loading, i.e. the same prescribed
+        macroscopic strain increment, and the current microstructure (the
+        densities as the increment and the DRX update left them, so the slip
+        resistances of the softened nuclei); the new stress, compatible and
+        mean strain and the plastic strain of the repeated increment replace
+        the old ones. Densities, grains, orientations and time stay."""
+        self.epsp = before["epsp"].copy()
+        self.sigma = before["sigma"].copy()
+        self.e = before["e"].copy()
+        self.E = before["E"].copy()
+        return self.increment(load, tol=tol, max_iter=max_iter, mechanics_only=True)
+
     # -- one increment ----------------------------------------------------
-    def increment(self, load: Loading, tol=1e-6, max_iter=1000, history=False):
+    def increment(self, load: Loading, tol=1e-6, max_iter=1000, history=False, mechanics_only=False):
+        """One strain increment. mechanics_only: advance only the stress,
+        strain and plastic strain (the repeated solve of a redistribution):
+        densities, GND densities, orientations and time are not updated."""
         self._dt = load.dt
         sc = np.asarray(load.strain_ctrl).astype(bool)
         s = ~sc
@@ -261,16 +288,22 @@ class Oracle:
             _, gdot = L.slip_rates(sig, self.m, tauc, self._gdot0(), f.n)
             self.epsp = self.epsp + load.dt * np.einsum("ma,mak->mk", gdot, self.m)
             gsum = np.abs(gdot).sum(axis=1)
-            self.rho = self.rho + load.dt * (f.k1 * np.sqrt(self.rho) - f.k2 * self.rho) * gsum
+            if not mechanics_only:
+                self.rho = self.rho + load.dt * (f.k1 * np.sqrt(self.rho) - f.k2 * self.rho) * gsum
         else:
             tau_a = L.resolved_shear(sig, self.m)
             gdot = mflow.rate(tau_a)
             epdot = np.einsum("ma,mak->mk", gdot, self.m)
             self.epsp = self.epsp + load.dt * epdot
-            self.ssd = self.ssd + load.dt * MR.ssd_rates(self.mr, self.ssd, rF, rP, tau_a, gdot,
-                                                         MR.von_mises_stress(sig), MR.von_mises_rate(epdot))
-            self.rho = self.ssd.sum(axis=1)
+            if not mechanics_only:
+                self.ssd = self.ssd + load.dt * MR.ssd_rates(self.mr, self.ssd, rF, rP, tau_a, gdot,
+                                                             MR.von_mises_stress(sig), MR.von_mises_rate(epdot))
+                self.rho = self.ssd.sum(axis=1)
         self.sigma, self.e, self.E = sig, e, E
+        if mechanics_only:
+            return dict(iters=iters, converged=converged, err_c=err_c, err_bc=err_bc,
+                        Sigma=mandel_to_voigt(sig.mean(axis=0)), E=mandel_to_voigt(E),
+                        rho_mean=float(self.rho.mean()), newton_fail=nfail)
         if self.gnd is not None:
             G = self.gnd
             rs, ret = gnd_rates(gdot.T, self.quat, G["grains"], self.shape, f.b, G["leff"])

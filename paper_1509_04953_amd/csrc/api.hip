@@ -25,8 +25,9 @@ struct Bufs {
   void* rho = nullptr;     // [V]
   void* epsp = nullptr;    // [6][V]
   void* sig[2] = {};       // committed / working stress, [6][V]
-  void* emain[3] = {};     // x-half-spectra of strain, [6][V/2] complex
-  void* enyq[3] = {};      // x-Nyquist planes, [6][n1 n2]
+  void* emain[4] = {};     // x-half-spectra of strain, [6][V/2] complex (the fourth: allocated
+  void* enyq[4] = {};      // by set_drx for the stress redistribution); x-Nyquist planes, [6][n1 n2]
+  void* epsp0 = nullptr;   // redistribution: plastic strain before the repeated increment, [6][V]
   void* tmain = nullptr;   // polarisation spectra, [6][V/2] complex
   void* tw[3] = {};        // twiddles per axis
   // adjoint workspaces (allocated on first use)
@@ -311,6 +312,7 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.kappa);
   f(ctx->b.grain2);
   f(ctx->b.estore);
+  f(ctx->b.epsp0);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->b.a_eta);
   f(ctx->b.a_sigt);
@@ -417,7 +419,10 @@ struct SolveOut {
 template <typename T, int MODE>
 fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0 c0, FinArgs& fin,
                          const double* E_start, const double* dE, const void* lam0, const void* epsp,
-                         const void* rho, const void* sig_t, SolveOut& out) {
+                         const void* rho, const void* sig_t, SolveOut& out, int start_buf = -1) {
+  // the first iteration reads the strain in start_buf (default: the committed
+  // buffer); the iterations write only the two buffers other than the committed one
+  if (start_buf < 0) start_buf = ctx->ec;
   Ctl h{};
   for (int k = 0; k < 6; ++k) h.E[k] = E_start[k];
   *ctx->ctl_h = h;
@@ -428,7 +433,7 @@ fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0
   while (launched < o.max_iter) {
     const int upto = std::min(o.max_iter, launched + chunk);
     for (int i = launched; i < upto; ++i) {
-      const int in = i == 0 ? ctx->ec : w[(i - 1) % 2];
+      const int in = i == 0 ? start_buf : w[(i - 1) % 2];
       const int ob = w[i % 2];
       const void* lam = i == 0 ? lam0 : ctx->b.sig[ctx->sw];
       HIPCHK((enqueue_iteration<T, MODE>(ctx, i, in, ob, lam, ctx->b.sig[ctx->sw], epsp, rho, sig_t, m,
@@ -446,7 +451,7 @@ fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0
   out.done = out.ctl.done;
   const int k = out.iters - 1;
   // buffer holding the strain of the latest completed iteration
-  if (out.done == 1) ctx->e_last = k == 0 ? ctx->ec : w[(k - 1) % 2];
+  if (out.done == 1) ctx->e_last = k == 0 ? start_buf : w[(k - 1) % 2];
   else ctx->e_last = w[k % 2];
   return FFTEVP_OK;
 }
@@ -523,6 +528,7 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     sa.k2 = ctx->flow.k2;
     sa.m = m;
     sa.gd = (ctx->gnd_on || ctx->rot_on) ? (T*)ctx->b.gd : nullptr;
+    sa.dens = 1;
     if (ctx->law == 1) {
       sa.ssd = (T*)ctx->b.ssd;
       sa.sysp = (const T*)ctx->b.sysp;
@@ -587,6 +593,121 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     rep->rho_mean = rho_mean;
     rep->newton_mean = so.ctl.nsum / (double)ctx->V;
     rep->linesearch_mean = so.ctl.lssum / (double)ctx->V;
+    rep->l_eff = ctx->gnd_on ? ctx->leff : 0.0;
+  }
+  return ret;
+}
+
+size_t snap_layout(const fftevp_ctx* c, size_t off[9]);
+
+// Stress redistribution (Sec. 2.5): the last increment's solve repeated from
+// the mechanical state of the snapshot taken before it (plastic strain,
+// stress, compatible strain, mean strain), with the same loading and the
+// current densities (hence slip resistances), grains and orientations. The
+// start state goes into buffers the committed state does not use (the
+// working stress, the fourth strain buffer, epsp0), so a solve that fails
+// changes nothing; on success stress, strain, mean strain and plastic strain
+// (start value + dt * rate at the new stress) are committed, the densities,
+// GND densities, effective length, orientations and time are not advanced.
+template <typename T>
+fftevp_status redistribute_impl(fftevp_ctx* ctx, const fftevp_opts& o, const void* before, fftevp_report* rep) {
+  double hdr[kHeader];
+  HIPCHK(hipMemcpyAsync(hdr, before, sizeof hdr, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (hdr[0] != kSnapMagic || hdr[1] != (double)ctx->prec || hdr[2] != ctx->n0 || hdr[3] != ctx->n1 ||
+      hdr[4] != ctx->n2 || hdr[14] != (ctx->gnd_on ? 1.0 : 0.0) || hdr[16] != (double)ctx->law ||
+      hdr[17] != (ctx->drx_on ? 1.0 : 0.0) || hdr[18] != (ctx->rot_on ? 1.0 : 0.0))
+    return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
+  const double dt = ctx->load.dt;
+  if (!(std::fabs(hdr[11] + dt - ctx->t) <= 1e-9 * std::max(dt, ctx->t)))
+    return fail(ctx, FFTEVP_EINVAL, "the snapshot must be the state one increment before the current one");
+  size_t off[9];
+  snap_layout(ctx, off);
+  const size_t V = ctx->V, ts = sizeof(T);
+  const char* s = (const char*)before;
+  HIPCHK(hipMemcpyAsync(ctx->b.epsp0, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.sig[ctx->sw], s + off[2], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.emain[3], s + off[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.enyq[3], s + off[4], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  const C0 c0 = reference_medium(ctx, &o);
+  Mat m = make_mat(ctx, c0, dt, sizeof(T) == 8 ? 1e-12 : 1e-5, o.newton_max);
+  m.qtol = sizeof(T) == 8 ? 1e-7 : 3e-4;
+  FinArgs fin = make_fin(ctx, o, c0);
+  double Edot[6], E0[6], E1[6], dE[6];
+  to_mandel(ctx->load.Edot, Edot);
+  for (int k = 0; k < 6; ++k) {
+    E0[k] = hdr[5 + k];
+    E1[k] = E0[k] + (ctx->load.strain_ctrl[k] ? Edot[k] * dt : 0.0);
+    dE[k] = E1[k] - E0[k];
+  }
+  SolveOut so;
+  fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, E1, dE, ctx->b.sig[ctx->sw], ctx->b.epsp0,
+                                                ctx->b.rho, nullptr, so, 3);
+  if (st != FFTEVP_OK) return st;
+  fftevp_status ret = FFTEVP_OK;
+  double rho_mean = 0.0;
+  if (so.done == 2) {
+    ret = fail(ctx, FFTEVP_ENONFINITE, "non-finite residual or mean stress");
+  } else if (so.done != 1) {
+    ret = fail(ctx, FFTEVP_NOT_CONVERGED, "max_iter reached");
+  } else {
+    if (so.iters == 1) {
+      // converged at the first iterate: its strain is the start state plus dE,
+      // moved into a buffer of the committed rotation
+      const int w0 = (ctx->ec + 1) % 3;
+      HIPCHK(hipMemcpyAsync(ctx->b.emain[w0], ctx->b.emain[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->b.enyq[w0], ctx->b.enyq[3], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+      HIPCHK(launch_shift_dc<T>((cx<T>*)ctx->b.emain[w0], ctx->planes, ctx->n0 / 2, dE, ctx->stream));
+      ctx->ec = w0;
+    } else {
+      ctx->ec = ctx->e_last;
+    }
+    ctx->e_last = ctx->ec;
+    std::swap(ctx->sc, ctx->sw);
+    for (int q = 0; q < 6; ++q) ctx->E[q] = so.ctl.E[q];
+    HIPCHK(hipMemcpyAsync(ctx->b.epsp, ctx->b.epsp0, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    StateArgs<T> sa{};
+    sa.sig = (const T*)ctx->b.sig[ctx->sc];
+    sa.quat = (const T*)ctx->b.quat;
+    sa.epsp = (T*)ctx->b.epsp;
+    sa.rho = (T*)ctx->b.rho;
+    sa.partial = ctx->partial;
+    sa.nvox = V;
+    sa.dt = dt;
+    sa.gdot0 = ctx->flow.gdot0;
+    sa.k1 = ctx->flow.k1;
+    sa.k2 = ctx->flow.k2;
+    sa.m = m;
+    sa.gd = nullptr;
+    sa.dens = 0;
+    if (ctx->law == 1) {
+      sa.ssd = (T*)ctx->b.ssd;
+      sa.sysp = (const T*)ctx->b.sysp;
+      sa.gnds = ctx->gnd_on ? (const T*)ctx->b.gnds : nullptr;
+      sa.gndet = ctx->gnd_on ? (const T*)ctx->b.gndet : nullptr;
+      sa.mr = ctx->mrc;
+      HIPCHK(timed(ctx, 5, -1, [&] { return launch_state_mr<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    } else {
+      HIPCHK(timed(ctx, 5, -1, [&] { return launch_state<T>(sa, ctx->red_nb, ctx->red2, ctx->stream); }));
+    }
+    HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->prof) HIPCHK(harvest(ctx, 0, false));
+    rho_mean = ctx->red2_h[0] / (double)V;
+    if (so.ctl.nfail > 0) ret = fail(ctx, FFTEVP_ELOCAL, "some voxel Newton solves reached newton_max");
+  }
+  if (rep) {
+    rep->iters = so.iters;
+    rep->newton_max_seen = (int)so.ctl.nmax;
+    rep->newton_failed = (int)so.ctl.nfail;
+    rep->err_c = so.ctl.err_c;
+    rep->err_bc = so.ctl.err_bc;
+    to_plain(so.ctl.Sigma, rep->Sigma);
+    to_plain(so.ctl.E, rep->E);
+    rep->rho_mean = rho_mean;
+    rep->newton_mean = so.ctl.nsum / (double)V;
+    rep->linesearch_mean = so.ctl.lssum / (double)V;
     rep->l_eff = ctx->gnd_on ? ctx->leff : 0.0;
   }
   return ret;
@@ -903,6 +1024,10 @@ fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double*
   void* kap = ctx->b.kappa;
   if (!kap) e = hipMalloc(&kap, V * ctx->tsize);
   if (e == hipSuccess && !ctx->b.grain2) e = hipMalloc((void**)&ctx->b.grain2, V * sizeof(int));
+  // buffers of the stress redistribution (fftevp_redistribute)
+  if (e == hipSuccess && !ctx->b.epsp0) e = hipMalloc(&ctx->b.epsp0, 6 * V * ctx->tsize);
+  if (e == hipSuccess && !ctx->b.emain[3]) e = hipMalloc(&ctx->b.emain[3], 6 * V * ctx->tsize);
+  if (e == hipSuccess && !ctx->b.enyq[3]) e = hipMalloc(&ctx->b.enyq[3], 6 * ctx->planes * ctx->tsize);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     if (kap && kap != ctx->b.kappa) (void)hipFree(kap);
@@ -1176,6 +1301,19 @@ fftevp_status fftevp_step_noalloc(fftevp_ctx* ctx, const fftevp_opts* opts, ffte
   ctx->red2 = red2;
   ctx->prof = prof;
   return st;
+}
+
+fftevp_status fftevp_redistribute(fftevp_ctx* ctx, const void* state_before_dev, const fftevp_opts* opts,
+                                  fftevp_report* out) {
+  if (!ctx || !state_before_dev) return fail(ctx, FFTEVP_EINVAL, "null argument");
+  if (!ctx->drx_on) return fail(ctx, FFTEVP_ESTATE, "stress redistribution follows DRX updates (fftevp_set_drx)");
+  if (!ctx->state_ok)
+    return fail(ctx, FFTEVP_ESTATE, "an adjoint solve reused the state buffers: load a snapshot first");
+  if (opts && (!(opts->tol >= 0.0) || opts->c0_mu < 0.0 || (opts->c0_mu > 0.0 && !(opts->c0_lambda + 2.0 * opts->c0_mu / 3.0 > 0.0))))
+    return fail(ctx, FFTEVP_EINVAL, "bad options");
+  const fftevp_opts o = resolve_opts(ctx, opts);
+  return ctx->prec == FFTEVP_FP64 ? redistribute_impl<double>(ctx, o, state_before_dev, out)
+                                  : redistribute_impl<float>(ctx, o, state_before_dev, out);
 }
 
 fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {

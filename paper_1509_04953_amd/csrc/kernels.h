@@ -148,6 +148,7 @@ struct StateArgs {
   T* rho;
   double* partial;  // [blocks][2]: sum rho_new, sum sum_a |gdot_a|
   T* gd;            // optional out: slip rates of the increment, [12][V] (GND update)
+  int dens;         // 1: advance the densities too; 0: plastic strain only
   size_t nvox;
   double dt, gdot0, k1, k2;
   Mat m;

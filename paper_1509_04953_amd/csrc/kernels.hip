@@ -793,8 +793,8 @@ __global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
     for (int k = 0; k < 6; ++k) dpc[k] = a.gdot0 * (k < 3 ? kUN : kUS) * gk[k];
     to_sample(R, dpc, dp);
     for (int k = 0; k < 6; ++k) a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
-    const double rn = rho + a.dt * (a.k1 * sqrt(rho) - a.k2 * rho) * a.gdot0 * asum;
-    a.rho[g] = (T)rn;
+    const double rn = a.dens ? rho + a.dt * (a.k1 * sqrt(rho) - a.k2 * rho) * a.gdot0 * asum : rho;
+    if (a.dens) a.rho[g] = (T)rn;
     if (a.gd) {
       // the increment's slip rates for the GND update: gdot0 |x|^(n-1) x
       const double itauc = 1.0 / tauc;
@@ -1145,12 +1145,12 @@ __global__ __launch_bounds__(256) void k_state_mr(StateArgs<T> a) {
       const double ddip = ag > 0.0 ? a.mr.dd_c / fabs(tau[al]) : 0.0;
       const double rate = a.mr.c4 * sqrt(F[al]) * ag + a.mr.c6 * ddip * rhom * ag - a.mr.c5 * rho * ag -
                           climb_f * rho * rho;
-      const double rn = rho + a.dt * rate;
-      a.ssd[(size_t)al * V + g] = (T)rn;
+      const double rn = a.dens ? rho + a.dt * rate : rho;
+      if (a.dens) a.ssd[(size_t)al * V + g] = (T)rn;
       tot += (double)(T)rn;
       if (a.gd) a.gd[(size_t)al * V + g] = (T)gd[al];
     }
-    a.rho[g] = (T)tot;
+    if (a.dens) a.rho[g] = (T)tot;
     part[0] += (double)(T)tot;
     part[1] += gsum;
   }

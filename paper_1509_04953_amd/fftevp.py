@@ -86,6 +86,7 @@ def library():
         "fftevp_drx_nucleate": (I, [P, P, C.POINTER(C.c_longlong)]),
         "fftevp_step": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_step_noalloc": (I, [P, C.POINTER(OptsC), C.POINTER(ReportC)]),
+        "fftevp_redistribute": (I, [P, P, C.POINTER(OptsC), C.POINTER(ReportC)]),
         "fftevp_get_field": (I, [P, I, P]),
         "fftevp_state_bytes": (S, [P]),
         "fftevp_save_state": (I, [P, P]),
@@ -284,14 +285,29 @@ class Solver:
         self._check(self.lib.fftevp_set_rotation(self.h, int(bool(on))))
 
     def drx_cycle(self, pf: "PhaseField", u, pf_steps: int, opts: Opts | None = None, zeta: float = 0.25,
-                  omega_gb: float = 0.625, dx: float = 10.7e-6):
+                  omega_gb: float = 0.625, dx: float = 10.7e-6, redistribute: bool = True):
         """One increment of the coupled loop (Sec. 2.5): the mechanical solve,
-        the nucleation test with fresh uniforms ``u``, then ``pf_steps`` steps
-        of grain growth. Returns (report, nuclei, changed, recrystallised)."""
+        the nucleation test with fresh uniforms ``u``, ``pf_steps`` steps of
+        grain growth, then the stress redistribution (the increment's solve
+        repeated with the updated microstructure). Returns (report, nuclei,
+        changed, recrystallised, redistribution report or None)."""
+        before = self.save_state()
         r = self.step(opts, allow=(OK,))
         n = self.drx_nucleate(u)
         changed, rex = self.drx_grow(pf, pf_steps, zeta, omega_gb, dx)
-        return r, n, changed, rex
+        rr = self.redistribute(before, opts, allow=(OK,)) if redistribute else None
+        return r, n, changed, rex, rr
+
+    def redistribute(self, before, opts: Opts | None = None, allow=(OK, NOT_CONVERGED, ELOCAL)) -> Report:
+        """fftevp_redistribute: the last increment's solve repeated from the
+        snapshot ``before`` (taken just before it) with the current
+        microstructure (stress redistribution after DRX, Sec. 2.5)."""
+        r = ReportC()
+        st = self._check(self.lib.fftevp_redistribute(self.h, C.c_void_p(before.data_ptr()),
+                                                      C.byref(_opts(opts)), C.byref(r)), allow)
+        return Report(st, r.iters, r.newton_max_seen, r.newton_failed, r.err_c, r.err_bc,
+                      np.array(r.Sigma[:]), np.array(r.E[:]), r.rho_mean, r.newton_mean,
+                      r.linesearch_mean, r.l_eff)
 
     def set_gnd(self, grains, l0: float = 21.4e-6, xi: float = 200.0):
         """Track GND densities (screw and edge, per slip system) from every

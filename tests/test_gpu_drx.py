@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import Oracle, Loading
+from oracle import Oracle, Loading, Flow
 from oracle import drx as ODX
 from oracle import ma_roters as OMR
 
@@ -205,12 +205,106 @@ def test_coupled_loop_matches_oracle(require_gpu, law):
     for inc in range(3):
         print(f"case: coupled {law} increment {inc}", flush=True)
         u = rng.random(V)
-        r, n, changed, rex = s.drx_cycle(pf, u, 12, Opts(tol=1e-11, max_iter=3000), dx=1.0e-3)
+        r, n, changed, rex, rr = s.drx_cycle(pf, u, 12, Opts(tol=1e-11, max_iter=3000), dx=1.0e-3)
+        before = o.mechanical_state()
         ro = o.increment(Loading(), tol=1e-11, max_iter=3000)
         no = o.drx_nucleate(u)
         co = o.drx_grow(12, 0.25, 0.625, 1.0e-3)
+        rro = o.redistribute(before, Loading(), tol=1e-11, max_iter=3000)
         assert r.iters == ro["iters"] and n == no and (changed, rex) == co, (inc, n, no, changed, rex, co)
+        assert rr.iters == rro["iters"], (inc, rr.iters, rro["iters"])
         assert np.array_equal(s.field("grain").cpu().numpy(), o.field("grain"))
-        for k in ("sigma", "rho_gnds", "rho_gndet"):
+        for k in ("sigma", "strain", "epsp", "rho_gnds", "rho_gndet"):
             assert rel(s.field(k).cpu().numpy(), o.field(k)) < 1e-10, (inc, k)
     pf.close()
+
+
+def _drx_pair(law, shape=(16, 16, 16), k12=None):
+    from paper_1509_04953_amd import Solver, Material, MaRoters, Load
+    V = int(np.prod(shape))
+    g = [np.random.default_rng(s) for s in np.random.SeedSequence(81).spawn(4)]
+    grains = synth.voronoi_grains(shape, 8, g[0])
+    q = synth.random_quaternions(8, g[1])
+    quat = np.moveaxis(q[grains], -1, 0).reshape(4, -1).copy()
+    rho = synth.lognormal_rho(shape, 2.5e12, 0.3, g[2]).reshape(-1)
+    mat = Material() if k12 is None else Material(k1=k12[0], k2=k12[1])
+    flow = Flow() if k12 is None else Flow(k1=k12[0], k2=k12[1])
+    s = Solver(shape)
+    s.set_material(mat)
+    s.set_microstructure(quat, rho)
+    s.set_loading(Load())
+    s.set_gnd(grains.reshape(-1))
+    o = Oracle(shape, quat, rho, flow=flow)
+    o.enable_gnd(grains.reshape(-1), 21.4e-6, 200.0)
+    if law == "paper":
+        s.set_law(MaRoters())
+        o.enable_mr(OMR.MaRoters())
+    u0 = np.random.default_rng(82).random(V)
+    kc = 3.2e12 if law == "paper" else 2.4e12
+    s.set_drx(u0, kc=kc)
+    o.enable_drx(ODX.DRX(kc=kc), u0)
+    return s, o, V
+
+
+def test_redistribution_matches_oracle(require_gpu):
+    """Stress redistribution (Sec. 2.5) with the paper's law and GND densities:
+    two increments, nucleation, then the last increment repeated from its
+    start state with the softened nuclei. The stress changes by several MPa
+    and matches the oracle within 1e-10, with equal iteration counts; a
+    snapshot from another time is refused."""
+    from paper_1509_04953_amd import Opts, FftevpError, EINVAL
+    s, o, V = _drx_pair("paper")
+    opts = Opts(tol=1e-11, max_iter=3000)
+    print("case: redistribution paper's law 16^3", flush=True)
+    old = s.save_state()
+    for _ in range(2):
+        before, before_o = s.save_state(), o.mechanical_state()
+        r = s.step(opts)
+        ro = o.increment(Loading(), tol=1e-11, max_iter=3000)
+        assert r.iters == ro["iters"]
+    u = np.random.default_rng(83).random(V)
+    n = s.drx_nucleate(u)
+    assert n == o.drx_nucleate(u) and n > 20
+    sig0 = s.field("sigma").cpu().numpy()
+    with pytest.raises(FftevpError) as e:
+        s.redistribute(old, opts)
+    assert e.value.status == EINVAL
+    rr = s.redistribute(before, opts)
+    rro = o.redistribute(before_o, Loading(), tol=1e-11, max_iter=3000)
+    assert rr.status == 0 and rr.iters == rro["iters"], (rr.iters, rro["iters"])
+    sig = s.field("sigma").cpu().numpy()
+    assert np.abs(sig - sig0).max() > 1.0
+    for k in ("sigma", "strain", "epsp", "rho", "rho_ssd", "rho_gnds"):
+        assert rel(s.field(k).cpu().numpy(), o.field(k)) < 1e-10, k
+    assert np.abs(rr.Sigma - rro["Sigma"]).max() < 1e-10 * np.abs(rro["Sigma"]).max()
+    # the next increment continues from the redistributed state on both sides
+    r = s.step(opts)
+    ro = o.increment(Loading(), tol=1e-11, max_iter=3000)
+    assert r.iters == ro["iters"]
+    assert rel(s.field("sigma").cpu().numpy(), o.field("sigma")) < 1e-10
+    s.close()
+
+
+def test_redistribution_power_law_frozen_density_is_identity(require_gpu):
+    """With the power law and a density that does not evolve (k1 = k2 = 0)
+    nothing the repeated solve depends on has changed: it reproduces the
+    committed state bit for bit. Without set_drx the call is refused."""
+    from paper_1509_04953_amd import Solver, Opts, FftevpError, ESTATE
+    s, o, V = _drx_pair("power", k12=(0.0, 0.0))
+    opts = Opts(tol=1e-10, max_iter=3000)
+    print("case: redistribution power law, frozen density", flush=True)
+    s.step(opts)
+    before = s.save_state()
+    r = s.step(opts)
+    s.drx_nucleate(np.random.default_rng(84).random(V))
+    f0 = {k: s.field(k).cpu().numpy() for k in ("sigma", "strain", "epsp", "rho")}
+    rr = s.redistribute(before, opts)
+    assert rr.iters == r.iters
+    for k, v in f0.items():
+        assert np.array_equal(s.field(k).cpu().numpy(), v), k
+    s.close()
+    t = Solver((8, 8, 8))
+    with pytest.raises(FftevpError) as e:
+        t.redistribute(t.save_state())
+    assert e.value.status == ESTATE
+    t.close()

@@ -125,3 +125,57 @@ def test_growth_stored_energy_against_capillarity(factor, grows):
         assert gained > 50 and lost == 0, (gained, lost)
     else:
         assert lost > 50 and gained == 0, (gained, lost)
+
+
+def _nucleated(law, k12=None):
+    from oracle import Flow
+    from oracle import ma_roters as MR
+    import synth
+    shape = (8, 8, 8)
+    V = 512
+    g = [np.random.default_rng(s) for s in np.random.SeedSequence(3).spawn(4)]
+    grains = synth.voronoi_grains(shape, 4, g[0])
+    q = synth.random_quaternions(4, g[1])
+    quat = np.moveaxis(q[grains], -1, 0).reshape(4, -1).copy()
+    o = Oracle(shape, quat, np.full(V, 2.5e12), flow=Flow(k1=k12[0], k2=k12[1]) if k12 else None)
+    o.enable_gnd(grains.reshape(-1), 21.4e-6, 200.0)
+    if law == 1:
+        o.enable_mr(MR.MaRoters())
+    o.enable_drx(DX.DRX(kc=3.2e12 if law == 1 else 2.4e12), np.random.default_rng(5).random(V))
+    for _ in range(2):
+        before = o.mechanical_state()
+        r = o.increment(Loading(), tol=1e-10, max_iter=3000)
+    n = o.drx_nucleate(np.random.default_rng(6).random(V))
+    assert n > 20
+    return o, before, r
+
+
+def test_redistribution_power_law_frozen_density_is_identity():
+    """With the power law at a density that does not evolve, nothing the
+    repeated solve depends on changed: the committed state comes back
+    exactly (same iteration count)."""
+    o, before, r = _nucleated(0, (0.0, 0.0))
+    s0, e0, p0 = o.sigma.copy(), o.e.copy(), o.epsp.copy()
+    rr = o.redistribute(before, Loading(), tol=1e-10, max_iter=3000)
+    assert rr["iters"] == r["iters"]
+    assert np.array_equal(o.sigma, s0) and np.array_equal(o.e, e0) and np.array_equal(o.epsp, p0)
+
+
+def test_redistribution_paper_law_changes_only_the_mechanics():
+    """Paper's law with GND densities: after nucleation the repeated solve
+    moves the stress (the softened nuclei and the increment's hardening
+    enter the slip resistances), leaves densities, grains and time alone,
+    keeps the mean strain prescribed and <e> = E, and repeating it from the
+    same start state gives the same result."""
+    o, before, r = _nucleated(1)
+    s0 = o.sigma.copy()
+    dens = (o.ssd.copy(), o.gnd["rs"].copy(), o.gnd["grains"].copy(), o.t)
+    rr = o.redistribute(before, Loading(), tol=1e-10, max_iter=3000)
+    assert rr["converged"] and np.abs(o.sigma - s0).max() > 1.0
+    assert np.array_equal(o.ssd, dens[0]) and np.array_equal(o.gnd["rs"], dens[1])
+    assert np.array_equal(o.gnd["grains"], dens[2]) and o.t == dens[3]
+    assert abs(rr["E"][2] - r["E"][2]) < 1e-15
+    assert np.abs(o.e.mean(axis=0) - o.E).max() < 1e-12
+    s1, p1 = o.sigma.copy(), o.epsp.copy()
+    o.redistribute(before, Loading(), tol=1e-10, max_iter=3000)
+    assert np.array_equal(o.sigma, s1) and np.array_equal(o.epsp, p1)
