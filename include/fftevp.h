@@ -309,7 +309,12 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src_dev);
  * before the last increment): adjoint of the state after the increment on
  * entry, adjoint of the state before it on return. dL_dtheta[4] (host,
  * d/d(tau0, k1, k2, n)) is accumulated. The implicit linear problem is
- * solved with the same spectral iteration, to opts->tol. */
+ * solved with the same spectral iteration, to opts->tol; in MIXED precision
+ * to max(opts->tol, 1e-5), since FP32 fields stall the tangent residual
+ * near that level once the adjoint state has accumulated over many
+ * increments (the gradient is then within ~1e-5 of the FP64 one). The call
+ * allocates nothing: it reuses the context's state buffers, so load a
+ * snapshot before the next fftevp_step (ESTATE otherwise). */
 size_t fftevp_adjoint_bytes(const fftevp_ctx* ctx);
 fftevp_status fftevp_adjoint_increment(fftevp_ctx* ctx, const fftevp_opts* opts,
                                        const void* state_before_dev,

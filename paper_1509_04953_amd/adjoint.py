@@ -34,6 +34,7 @@ class CurveProblem:
     opts: Opts = None
     adjoint_opts: Opts = None
     checkpoint_every: int = 0
+    iterations: list = None   # fixed-point iterations of the latest forward, per increment
 
 
 def _material(base: Material, theta) -> Material:
@@ -48,11 +49,13 @@ def _forward(p: CurveProblem, theta, keep_every):
     s.set_loading(p.load)
     ckpts = {0: s.save_state()}
     curve = []
+    p.iterations = []
     for t in range(1, p.increments + 1):
         r = s.step(p.opts)
         if r.status != OK:
             raise RuntimeError(f"increment {t} did not converge (status {r.status})")
         curve.append(r.Sigma[2])
+        p.iterations.append(r.iters)
         if keep_every and t % keep_every == 0 and t < p.increments:
             ckpts[t] = s.save_state()
     return np.array(curve), ckpts

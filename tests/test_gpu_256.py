@@ -119,3 +119,28 @@ def test_256_adjoint_checkpointed(require_gpu, micro):
     print("mixed adjoint", gm, flush=True)
     assert (np.abs(gm - g) / np.abs(g)).max() < 1e-3
     pm.solver.close()
+
+
+def test_256_mixed_twelve_increments_checkpoint_schedules(require_gpu, micro):
+    """The configuration's own form (mixed precision, stop tolerance 1e-6,
+    adjoint with checkpointing) over 12 increments (2.4 % strain): the curve
+    hardens monotonically, the schedules ceil(sqrt 12) = 4 and 5 give
+    bit-identical curves and gradients, and the gradient of the loss against
+    a zero target has the signs a harder material implies (those of the
+    single-crystal recursion: +, +, -, +)."""
+    th0 = np.array([5.0, 8.0e7, 10.0, 10.0])
+    tgt = np.zeros(12)
+    print("case: 256^3 mixed adjoint, 12 increments, checkpoints every 4", flush=True)
+    p4 = _problem(micro, "mixed", 4, W.tol, 12)
+    c4, g4 = _grad(p4, th0, tgt)
+    assert all(i > 0 for i in p4.iterations)
+    p4.solver.close()
+    print("case: 256^3 mixed adjoint, 12 increments, checkpoints every 5", flush=True)
+    p5 = _problem(micro, "mixed", 5, W.tol, 12)
+    c5, g5 = _grad(p5, th0, tgt)
+    p5.solver.close()
+    assert np.array_equal(c4, c5) and np.array_equal(g4, g5), (g4, g5)
+    assert np.all(np.diff(-c4) > 0), c4          # compression: |s33| grows
+    # with a zero target dL/dtheta = mean 2 s33 ds33/dtheta: a harder
+    # material (larger tau0, k1, n; smaller k2) makes s33 more negative
+    assert g4[0] > 0 and g4[1] > 0 and g4[2] < 0 and g4[3] > 0, g4
