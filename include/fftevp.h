@@ -254,12 +254,16 @@ fftevp_status fftevp_redistribute(fftevp_ctx* ctx, const void* state_before_dev,
 
 /* Lattice rotation (reading of the orientation change of Sec. 2.5; the
  * paper gives no equation): on = 1 turns, after every committed increment
- * (after the GND update), each voxel's lattice by exp(dt Omega_e) with
- * Omega_e = -sum_a gdot_a skew(d_a (x) n_a), the increment's slip rates and
- * the sample-frame unit slip direction d_a and plane normal n_a; the imposed
- * spin is zero and the local spin of the spectral solution is not included.
- * Orientations then enter snapshots; the adjoint is unavailable (EINVAL).
- * on = 0 (default) keeps them fixed. EINVAL unless on is 0 or 1. */
+ * (after the GND update), each voxel's lattice by exp(dw - dt Omega_p) with
+ * Omega_p = sum_a gdot_a skew(d_a (x) n_a) (the increment's slip rates, the
+ * sample-frame unit slip direction d_a and plane normal n_a) and dw the
+ * local rigid rotation of the increment: the antisymmetric part of the
+ * gradient of the periodic displacement fluctuation whose symmetric part is
+ * the increment's compatible strain change, computed spectrally (axial
+ * vector n x (e n) per wave direction n; none at the mean and at Nyquist
+ * frequencies). The imposed macroscopic spin is zero. Orientations then
+ * enter snapshots; the adjoint is unavailable (EINVAL). on = 0 (default)
+ * keeps them fixed. EINVAL unless on is 0 or 1. */
 fftevp_status fftevp_set_rotation(fftevp_ctx* ctx, int on);
 
 /* One strain increment: the fixed-point solve, then the explicit update of

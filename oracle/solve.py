@@ -299,6 +299,7 @@ class Oracle:
                 self.ssd = self.ssd + load.dt * MR.ssd_rates(self.mr, self.ssd, rF, rP, tau_a, gdot,
                                                              MR.von_mises_stress(sig), MR.von_mises_rate(epdot))
                 self.rho = self.ssd.sum(axis=1)
+        e_start = self.e
         self.sigma, self.e, self.E = sig, e, E
         if mechanics_only:
             return dict(iters=iters, converged=converged, err_c=err_c, err_bc=err_bc,
@@ -311,9 +312,11 @@ class Oracle:
             G["ret"] = G["ret"] + load.dt * ret
             G["leff"] = next_leff(G["leff"], E, G["xi"])
         if self.rot:
-            # lattice rotation from the increment's slip rates (oracle.rotation),
-            # after the GND update, which uses the orientation they acted in
-            self.quat = ROT.rotate(self.quat, gdot, load.dt)
+            # lattice rotation from the local rotation of the increment's strain
+            # change and its slip rates (oracle.rotation), after the GND update,
+            # which uses the orientation they acted in
+            dw = ROT.local_rotation(e - e_start, self.shape)
+            self.quat = ROT.rotate(self.quat, gdot, load.dt, dw)
             self.C, self.S, self.m = voxel_material(self.quat, *self.elastic)
         self.t += load.dt
         rep = dict(iters=iters, converged=converged, err_c=err_c, err_bc=err_bc,

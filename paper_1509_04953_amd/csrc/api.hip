@@ -28,6 +28,7 @@ struct Bufs {
   void* emain[4] = {};     // x-half-spectra of strain, [6][V/2] complex (the fourth: allocated
   void* enyq[4] = {};      // by set_drx for the stress redistribution); x-Nyquist planes, [6][n1 n2]
   void* epsp0 = nullptr;   // redistribution: plastic strain before the repeated increment, [6][V]
+  double* spin = nullptr;  // lattice rotation: local rotation of the increment (axial), [3][V] FP64
   void* tmain = nullptr;   // polarisation spectra, [6][V/2] complex
   void* tw[3] = {};        // twiddles per axis
   // GND densities (allocated by set_gnd)
@@ -309,6 +310,7 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.grain2);
   f(ctx->b.estore);
   f(ctx->b.epsp0);
+  f(ctx->b.spin);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->partial);
   f(ctx->stage1);
@@ -471,6 +473,50 @@ fftevp_opts resolve_opts(const fftevp_ctx* ctx, const fftevp_opts* in) {
   return o;
 }
 
+// Local rotation of the committed increment (axial vector per voxel, FP64,
+// into b.spin): the strain change e_new - e_old of the x-half-spectra, then
+// the forward y pass (without the reduction row), the z pass that maps each
+// compatible mode to its rotation, the inverse y pass and the inverse real
+// x-FFT of the export path (x-Nyquist plane zero). Uses the polarisation
+// buffer and the third strain buffer, both free between increments.
+template <typename T>
+hipError_t local_spin(fftevp_ctx* ctx, int e_new, int e_old) {
+  using C = cx<T>;
+  hipError_t e = launch_cdiff<T>((const C*)ctx->b.emain[e_new], (const C*)ctx->b.emain[e_old], (C*)ctx->b.tmain,
+                                 3 * ctx->V, ctx->stream);
+  if (e != hipSuccess) return e;
+  YArgs<T> ya{};
+  ya.src = (const C*)ctx->b.tmain;
+  ya.dst = (C*)ctx->b.tmain;
+  ya.tw = (const C*)ctx->b.tw[1];
+  ya.h = ctx->n0 / 2;
+  ya.no_reduce = 1;
+  if ((e = launch_ypass<T, false>(ctx->n1, ctx->n2, ya, ctx->stream)) != hipSuccess) return e;
+  ZArgs<T> za{};
+  za.buf = (C*)ctx->b.tmain;
+  za.tw = (const C*)ctx->b.tw[2];
+  za.h = ctx->n0 / 2;
+  za.n1 = ctx->n1;
+  za.inv_n0 = 1.0 / ctx->n0;
+  za.inv_n1 = 1.0 / ctx->n1;
+  za.inv_n2 = 1.0 / ctx->n2;
+  za.inv_ntot = 1.0 / ((double)ctx->n1 * ctx->n2);  // the y and z round trips are unnormalised
+  if ((e = launch_zspin<T>(ctx->n2, za, ctx->stream)) != hipSuccess) return e;
+  ya.no_reduce = 0;
+  if ((e = launch_ypass<T, true>(ctx->n1, ctx->n2, ya, ctx->stream)) != hipSuccess) return e;
+  const int third = 3 - e_new - e_old;
+  if ((e = launch_fill<T>((T*)ctx->b.enyq[third], 6 * ctx->planes, T(0), ctx->stream)) != hipSuccess) return e;
+  LocalArgs<T> la{};
+  la.e_main = (const C*)ctx->b.tmain;
+  la.e_nyq = (const T*)ctx->b.enyq[third];
+  la.tw = (const C*)ctx->b.tw[0];
+  la.out = ctx->b.spin;
+  la.nout = 3;
+  la.n1 = ctx->n1;
+  la.n2 = ctx->n2;
+  return launch_local<T, MODE_EXPORT>(ctx->n0, la, ctx->stream);
+}
+
 template <typename T>
 fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* rep) {
   const C0 c0 = reference_medium(ctx, &o);
@@ -485,6 +531,7 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     dE[k] = E1[k] - ctx->E[k];
   }
   SolveOut so;
+  const int ec_start = ctx->ec;
   fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, E1, dE, ctx->b.sig[ctx->sc],
                                                 ctx->b.epsp, ctx->b.rho, nullptr, so);
   if (st != FFTEVP_OK) return st;
@@ -559,8 +606,13 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     }
     // lattice rotation from the same slip rates, after the GND update, which
     // uses the orientation they acted in
+    // plus the local rotation of the strain change (none when the first
+    // iterate converged: the change is then the uniform dE)
+    const bool spin = ctx->rot_on && ctx->ec != ec_start;
+    if (spin) HIPCHK(timed(ctx, 1, -1, [&] { return local_spin<T>(ctx, ctx->ec, ec_start); }));
     if (ctx->rot_on)
-      HIPCHK(timed(ctx, 1, -1, [&] { return launch_rotate<T>((T*)ctx->b.quat, (const T*)ctx->b.gd, ctx->V, dt,
+      HIPCHK(timed(ctx, 1, -1, [&] { return launch_rotate<T>((T*)ctx->b.quat, (const T*)ctx->b.gd,
+                                                              spin ? ctx->b.spin : nullptr, ctx->V, dt,
                                                               ctx->stream); }));
     // the next increment's frozen parameters of the paper's law
     if (ctx->law == 1) HIPCHK(mr_params(ctx));
@@ -1145,8 +1197,11 @@ fftevp_status fftevp_drx_grow(fftevp_ctx* ctx, fftevp_pf* pf, const fftevp_grow*
 fftevp_status fftevp_set_rotation(fftevp_ctx* ctx, int on) {
   if (!ctx) return fail(ctx, FFTEVP_EINVAL, "null argument");
   if (on != 0 && on != 1) return fail(ctx, FFTEVP_EINVAL, "on must be 0 or 1");
-  if (on && !ctx->b.gd) {
-    if (hipMalloc(&ctx->b.gd, 12 * ctx->V * ctx->tsize) != hipSuccess) {
+  if (on) {
+    hipError_t e = hipSuccess;
+    if (!ctx->b.gd) e = hipMalloc(&ctx->b.gd, 12 * ctx->V * ctx->tsize);
+    if (e == hipSuccess && !ctx->b.spin) e = hipMalloc((void**)&ctx->b.spin, 3 * ctx->V * sizeof(double));
+    if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(ctx, FFTEVP_ENOMEM, "device allocation failed");
     }

@@ -67,6 +67,7 @@ struct LocalArgs {
   const Ctl* ctl;
   const cx<T>* tw;      // twiddles for n0
   double* out;          // export mode: plain-component strain, [6][V] FP64
+  int nout;             // export mode: components written (0: all six)
   double dE[6];
   int add_dE;
   int n1, n2;
@@ -85,6 +86,7 @@ struct YArgs {
   const double* partial;
   int nb_local;
   double* stage1;
+  int no_reduce;  // forward pass without the reduction row (the local-rotation transform)
 };
 
 template <typename T>
@@ -195,6 +197,14 @@ template <typename T, bool INV>
 hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s);
+// local rotation of a strain increment: forward z-FFT, w = n x (e n) per
+// frequency (zero at xi = 0 and Nyquist) into components 0..2, scaled by
+// a.inv_ntot, inverse z-FFT; a.ctl unused
+template <typename T>
+hipError_t launch_zspin(int n2, const ZArgs<T>& a, hipStream_t s);
+// out = a - b, n complex values
+template <typename T>
+hipError_t launch_cdiff(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
 template <typename T>
@@ -214,7 +224,7 @@ template <typename T>
 hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, hipStream_t s);
 // lattice rotation by minus the plastic spin of the slip rates gd [12][V] over dt
 template <typename T>
-hipError_t launch_rotate(T* quat, const T* gd, size_t V, double dt, hipStream_t s);
+hipError_t launch_rotate(T* quat, const T* gd, const double* spin, size_t V, double dt, hipStream_t s);
 // scale x total dislocation density (Eq. 11) of every voxel into out [V]
 template <typename T>
 hipError_t launch_rho_tot(const DrxArgs<T>& a, bool mr, double scale, double* out, hipStream_t s);

@@ -230,8 +230,9 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
         const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
         const double f0 = (2 * p >= 3) ? kIR2 : 1.0;
         const double f1 = (2 * p + 1 >= 3) ? kIR2 : 1.0;
-        a.out[(size_t)(2 * p) * vox + g] = f0 * (double)z.x;
-        a.out[(size_t)(2 * p + 1) * vox + g] = f1 * (double)z.y;
+        const int nout = a.nout > 0 ? a.nout : 6;
+        if (2 * p < nout) a.out[(size_t)(2 * p) * vox + g] = f0 * (double)z.x;
+        if (2 * p + 1 < nout) a.out[(size_t)(2 * p + 1) * vox + g] = f1 * (double)z.y;
       }
     }
     return;
@@ -598,8 +599,9 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_ypass(YArgs<T> a) {
   if (a.ctl && a.ctl->done) return;
   int bx, by;
   xcd_tile(bx, by);
+  const bool red_row = !INV && !a.no_reduce;
   if constexpr (!INV) {
-    if (by == 0) {
+    if (red_row && by == 0) {
       const int ns = gridDim.x, nb = a.nb_local;
       const int chunk = (nb + ns - 1) / ns;
       const int b0 = bx * chunk, b1 = min(nb, b0 + chunk);
@@ -618,7 +620,7 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_ypass(YArgs<T> a) {
   constexpr int W = 6 * TX;
   __shared__ cx<T> sh[W * (N1 + 1)];
   const size_t rs = (size_t)a.h * 6;  // y stride
-  const size_t z = INV ? by : by - 1;
+  const size_t z = red_row ? by - 1 : by;
   const size_t base = z * N1 * rs + (size_t)bx * W;
   rows_to_lines<T, N1, W>(a.src + base, rs, sh);
   __syncthreads();
@@ -732,6 +734,70 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zgamma(ZArgs<T> a) {
   __syncthreads();
   fft_lines<T, N2, true, W, LS, 256>(sh, a.tw);
   lines_to_rows<T, N2, W>(sh, buf, zs);
+}
+
+// ---------------------------------------------------------------------------
+// z pass of the local rotation of a compatible strain increment
+// ---------------------------------------------------------------------------
+// For a compatible mode e(xi) = sym(i xi (x) u), the antisymmetric part of
+// i xi (x) u has the axial vector w = n x (e n), n = xi / |xi| (no frequency
+// scale enters). Forward z-FFT of the six components, w into components
+// 0..2 (zero elsewhere, and at xi = 0 and every Nyquist index, where the
+// solver's strain is not a gradient), times a.inv_ntot, inverse z-FFT.
+template <typename T, int N2, int TX>
+__global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zspin(ZArgs<T> a) {
+  constexpr int LS = N2 + 1;
+  constexpr int W = 6 * TX;
+  __shared__ cx<T> sh[W * LS];
+  int bx, by;
+  xcd_tile(bx, by);
+  const int H = a.h, n1 = a.n1;
+  const int ky = by, kx0 = bx * TX;
+  const size_t zs = (size_t)n1 * H * 6;
+  cx<T>* __restrict__ buf = a.buf + ((size_t)ky * H + kx0) * 6;
+  rows_to_lines<T, N2, W>(buf, zs, sh);
+  __syncthreads();
+  fft_lines<T, N2, false, W, LS, 256>(sh, a.tw);
+  const T scale = T(a.inv_ntot), h = T(kIR2);
+  const int ky_s = ky < n1 / 2 ? ky : ky - n1;
+  const bool nyq_y = (2 * ky == n1);
+  for (int idx = threadIdx.x; idx < N2 * TX; idx += 256) {
+    const int z = idx / TX, kx = idx - (idx / TX) * TX;
+    const int kz_s = z < N2 / 2 ? z : z - N2;
+    const int kxg = kx0 + kx;
+    cx<T> w[3] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    if (!(kxg == 0 && ky == 0 && z == 0) && !nyq_y && 2 * z != N2) {
+      cx<T> t[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) t[c] = sh[(kx * 6 + c) * LS + z];
+      const T fx = T(kxg) * T(a.inv_n0), fy = T(ky_s) * T(a.inv_n1), fz = T(kz_s) * T(a.inv_n2);
+      const T in = T(1) / sqrt(fx * fx + fy * fy + fz * fz);
+      const T nx = fx * in, ny = fy * in, nz = fz * in;
+      // v = e n (Mandel: e23 = h t3, e13 = h t4, e12 = h t5)
+      const cx<T> v0 = {t[0].x * nx + h * (t[5].x * ny + t[4].x * nz), t[0].y * nx + h * (t[5].y * ny + t[4].y * nz)};
+      const cx<T> v1 = {h * t[5].x * nx + t[1].x * ny + h * t[3].x * nz, h * t[5].y * nx + t[1].y * ny + h * t[3].y * nz};
+      const cx<T> v2 = {h * (t[4].x * nx + t[3].x * ny) + t[2].x * nz, h * (t[4].y * nx + t[3].y * ny) + t[2].y * nz};
+      w[0] = {scale * (ny * v2.x - nz * v1.x), scale * (ny * v2.y - nz * v1.y)};
+      w[1] = {scale * (nz * v0.x - nx * v2.x), scale * (nz * v0.y - nx * v2.y)};
+      w[2] = {scale * (nx * v1.x - ny * v0.x), scale * (nx * v1.y - ny * v0.y)};
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[(kx * 6 + c) * LS + z] = w[c];
+#pragma unroll
+    for (int c = 3; c < 6; ++c) sh[(kx * 6 + c) * LS + z] = {T(0), T(0)};
+  }
+  __syncthreads();
+  fft_lines<T, N2, true, W, LS, 256>(sh, a.tw);
+  lines_to_rows<T, N2, W>(sh, buf, zs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cdiff(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
+                                               cx<T>* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const cx<T> x = a[i], y = b[i];
+    out[i] = {x.x - y.x, x.y - y.y};
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -970,8 +1036,8 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
 // turns by exp(dt Omega_e): q <- (cos(|th|/2), sin(|th|/2) th/|th|) q with
 // th = dt times that axial vector, renormalised, w >= 0.
 template <typename T>
-__global__ __launch_bounds__(256) void k_rotate(T* __restrict__ quat, const T* __restrict__ gd, size_t V,
-                                                double dt) {
+__global__ __launch_bounds__(256) void k_rotate(T* __restrict__ quat, const T* __restrict__ gd,
+                                                const double* __restrict__ spin, size_t V, double dt) {
   for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < V; g += (size_t)gridDim.x * 256) {
     const double q0 = quat[g], q1 = quat[V + g], q2 = quat[2 * V + g], q3 = quat[3 * V + g];
     double u[3] = {0.0, 0.0, 0.0};  // sum_a gdot_a (integer n x d), crystal frame
@@ -987,6 +1053,11 @@ __global__ __launch_bounds__(256) void k_rotate(T* __restrict__ quat, const T* _
     double th[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) th[i] = c * (R[3 * i] * u[0] + R[3 * i + 1] * u[1] + R[3 * i + 2] * u[2]);
+    // plus the local rotation of the increment (axial vector, sample frame)
+    if (spin) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) th[i] += spin[(size_t)i * V + g];
+    }
     const double ang = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
     double a0 = 1.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (ang > 0.0) {
@@ -1555,7 +1626,8 @@ hipError_t ypass_tx(int n2, const YArgs<T>& a, hipStream_t s) {
   if constexpr (TX > 1) {
     if (a.h < TX) return ypass_tx<T, N, TX / 2, INV>(n2, a, s);
   }
-  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, n2 + (INV ? 0 : 1)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_ypass<T, N, TX, INV>), dim3(a.h / TX, n2 + (INV || a.no_reduce ? 0 : 1)), dim3(256), 0,
+                     s, a);
   return hipGetLastError();
 }
 
@@ -1594,6 +1666,35 @@ hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s) {
     case 512: return zgamma_tx<T, 512, spec_tile<T>(512)>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T, int N, int TX>
+hipError_t zspin_tx(const ZArgs<T>& a, hipStream_t s) {
+  if constexpr (TX > 1) {
+    if (a.h < TX) return zspin_tx<T, N, TX / 2>(a, s);
+  }
+  hipLaunchKernelGGL((k_zspin<T, N, TX>), dim3(a.h / TX, a.n1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zspin(int n2, const ZArgs<T>& a, hipStream_t s) {
+  switch (n2) {
+    case 8: return zspin_tx<T, 8, spec_tile<T>(8)>(a, s);
+    case 16: return zspin_tx<T, 16, spec_tile<T>(16)>(a, s);
+    case 32: return zspin_tx<T, 32, spec_tile<T>(32)>(a, s);
+    case 64: return zspin_tx<T, 64, spec_tile<T>(64)>(a, s);
+    case 128: return zspin_tx<T, 128, spec_tile<T>(128)>(a, s);
+    case 256: return zspin_tx<T, 256, spec_tile<T>(256)>(a, s);
+    case 512: return zspin_tx<T, 512, spec_tile<T>(512)>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_cdiff(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cdiff<T>, dim3(grid_for(n)), dim3(256), 0, s, a, b, out, n);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -1661,8 +1762,8 @@ hipError_t launch_drx(const DrxArgs<T>& a, bool mr, int nblocks, double* out2, h
 }
 
 template <typename T>
-hipError_t launch_rotate(T* quat, const T* gd, size_t V, double dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_rotate<T>, dim3(grid_for(V)), dim3(256), 0, s, quat, gd, V, dt);
+hipError_t launch_rotate(T* quat, const T* gd, const double* spin, size_t V, double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_rotate<T>, dim3(grid_for(V)), dim3(256), 0, s, quat, gd, spin, V, dt);
   return hipGetLastError();
 }
 
@@ -1740,7 +1841,9 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
                                       hipStream_t);                                           \
   template hipError_t launch_drx<T>(const DrxArgs<T>&, bool, int, double*, hipStream_t);      \
   template hipError_t launch_rho_tot<T>(const DrxArgs<T>&, bool, double, double*, hipStream_t); \
-  template hipError_t launch_rotate<T>(T*, const T*, size_t, double, hipStream_t);             \
+  template hipError_t launch_rotate<T>(T*, const T*, const double*, size_t, double, hipStream_t); \
+  template hipError_t launch_zspin<T>(int, const ZArgs<T>&, hipStream_t);                      \
+  template hipError_t launch_cdiff<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t); \
   template hipError_t launch_sweep<T>(const DrxArgs<T>&, int, double*, hipStream_t);          \
   template hipError_t launch_mr_params<T>(const T*, const T*, const T*, T*, size_t, const MrConst&, \
                                           hipStream_t);                                       \
