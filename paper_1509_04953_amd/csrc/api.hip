@@ -63,7 +63,8 @@ struct fftevp_ctx {
   int ec = 0;          // committed strain buffer
   int e_last = 0;      // strain buffer written by the latest iteration
   double* partial = nullptr;
-  double* stage1 = nullptr;  // [NPART][<= 64] first-stage sums of the y pass
+  double* stage1 = nullptr;  // [NPART][n_stage1] first-stage sums of the y pass
+  int n_stage1 = 0;          // x-frequency tiles of the y pass (blocks of its reduction row)
   int local_nb = 0, red_nb = 0;
   Ctl* ctl = nullptr;
   Ctl* ctl_h = nullptr;  // pinned
@@ -279,7 +280,8 @@ fftevp_status alloc_all(fftevp_ctx* ctx) {
   const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->partial, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->ctl, sizeof(Ctl));
-  if (e == hipSuccess) e = al((void**)&ctx->stage1, NPART * 64 * sizeof(double));
+  ctx->n_stage1 = ypass_tiles<T>(ctx->n1, ctx->n0 / 2);
+  if (e == hipSuccess) e = al((void**)&ctx->stage1, NPART * (size_t)ctx->n_stage1 * sizeof(double));
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->ctl_h, sizeof(Ctl), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&ctx->red2, 8 * sizeof(double));
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->red2_h, 8 * sizeof(double), hipHostMallocDefault);
@@ -379,7 +381,7 @@ hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, co
   za.tw = (const C*)ctx->b.tw[2];
   za.ctl = ctx->ctl;
   za.stage1 = ctx->stage1;
-  za.n_stage1 = ypass_tiles<T>(ctx->n1, ctx->n0 / 2);
+  za.n_stage1 = ctx->n_stage1;
   za.fin = fin;
   za.h = ctx->n0 / 2;
   za.n1 = ctx->n1;
@@ -1270,7 +1272,8 @@ fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_repor
 // ---------------------------------------------------------------------------
 // The increment's scratch is small next to its fields: the local kernel's
 // per-block partial sums (NPART per block of 256 voxels, or of 512 when
-// n0 = 512), the first-stage sums of the forward y pass (NPART x <= 64), the
+// n0 = 512), the first-stage sums of the forward y pass (NPART per
+// x-frequency tile, at most 256 tiles), the
 // control block, and the end-of-increment reduction pair. For grids of at
 // most 2^24 voxels it fits the array below; each device that runs the entry
 // point holds its own copy until the process ends.
@@ -1279,7 +1282,8 @@ constexpr size_t kNaMaxVoxels = size_t(1) << 24;
 constexpr size_t kNaPartial = kNaMaxVoxels / 256 * NPART;  // doubles (>= 1024 x 4)
 constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 constexpr size_t kNaOffStage1 = round256(kNaPartial * sizeof(double));
-constexpr size_t kNaOffCtl = kNaOffStage1 + round256(NPART * 64 * sizeof(double));
+constexpr int kNaMaxTiles = 256;  // x-frequency tiles of a y pass: n0 / 2 <= 256, at least one per tile
+constexpr size_t kNaOffCtl = kNaOffStage1 + round256(NPART * kNaMaxTiles * sizeof(double));
 constexpr size_t kNaOffRed2 = kNaOffCtl + round256(sizeof(Ctl));
 constexpr size_t kNaBytes = kNaOffRed2 + round256(8 * sizeof(double));
 static_assert(kNaPartial >= 1024 * 4, "the end-of-increment reduction needs 4096 partials");
@@ -1325,7 +1329,8 @@ fftevp_status fftevp_step_noalloc(fftevp_ctx* ctx, const fftevp_opts* opts, ffte
   if (ctx->V > kNaMaxVoxels)
     return fail(ctx, FFTEVP_EINVAL, "fftevp_step_noalloc: at most 2^24 voxels (use fftevp_step)");
   const size_t np = std::max((size_t)ctx->local_nb * NPART, (size_t)ctx->red_nb * 4);
-  if (np > kNaPartial) return fail(ctx, FFTEVP_EINVAL, "fftevp_step_noalloc: scratch too small for this grid");
+  if (np > kNaPartial || ctx->n_stage1 > kNaMaxTiles)
+    return fail(ctx, FFTEVP_EINVAL, "fftevp_step_noalloc: scratch too small for this grid");
   void* base = nullptr;
   const hipError_t e = na_scratch(ctx->stream, &base);
   if (e != hipSuccess) return fail(ctx, FFTEVP_EHIP, std::string("scratch address: ") + hipGetErrorString(e));

@@ -466,10 +466,24 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
 #define FFTEVP_Y_LDS_KB 25
 #endif
 
+// FP64 lines of 256 points or more get twice the budget: with 25 KB a tile
+// holds one x-frequency, whose 96-byte row segments straddle cache lines
+// that neighbouring tiles complete (measured at 256^3: the y passes wrote
+// 1.3x their bytes); two x-frequencies (49 KB, three blocks per CU) ran the
+// FP64 y and z passes 23-27 % faster there. FP32 tiles and shorter lines
+// measured fastest at 25 KB.
+#ifndef FFTEVP_SPEC_LDS_KB_F64_LONG
+#define FFTEVP_SPEC_LDS_KB_F64_LONG 50
+#endif
+template <typename T>
+__host__ __device__ constexpr int spec_budget_kb(int n, int kb) {
+  return (sizeof(T) == 8 && n >= 256) ? FFTEVP_SPEC_LDS_KB_F64_LONG : kb;
+}
 template <typename T>
 __host__ __device__ constexpr int spec_tile(int n, int kb = FFTEVP_SPEC_LDS_KB) {
   int tx = 16;
-  while (tx > 1 && 6 * tx * (n + 1) * 2 * (int)sizeof(T) > kb * 1024) tx /= 2;
+  const int budget = spec_budget_kb<T>(n, kb);
+  while (tx > 1 && 6 * tx * (n + 1) * 2 * (int)sizeof(T) > budget * 1024) tx /= 2;
   return tx;
 }
 template <typename T>
