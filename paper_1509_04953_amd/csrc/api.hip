@@ -19,15 +19,18 @@ namespace {
 
 constexpr double kSnapMagic = 5.09049531e7;  // tags a state snapshot
 constexpr int kHeader = 32;                  // doubles in a snapshot header
+constexpr int kSnapParts = 10;               // offsets of a snapshot layout
 
 struct Bufs {
   void* quat = nullptr;    // [4][V]
   void* rho = nullptr;     // [V]
   void* epsp = nullptr;    // [6][V]
+  void* q = nullptr;       // strain offset e - epsp of the committed state, [6][V] Mandel
   void* sig[2] = {};       // committed / working stress, [6][V]
   void* emain[4] = {};     // x-half-spectra of strain, [6][V/2] complex (the fourth: allocated
   void* enyq[4] = {};      // by set_drx for the stress redistribution); x-Nyquist planes, [6][n1 n2]
   void* epsp0 = nullptr;   // redistribution: plastic strain before the repeated increment, [6][V]
+  void* q0 = nullptr;      // redistribution: offset e - epsp before the repeated increment, [6][V]
   double* spin = nullptr;  // lattice rotation: local rotation of the increment (axial), [3][V] FP64
   void* tmain = nullptr;   // polarisation spectra, [6][V/2] complex
   void* tw[3] = {};        // twiddles per axis
@@ -264,6 +267,7 @@ fftevp_status alloc_all(fftevp_ctx* ctx) {
   if (e == hipSuccess) e = al(&ctx->b.quat, 4 * V * ts);
   if (e == hipSuccess) e = al(&ctx->b.rho, V * ts);
   if (e == hipSuccess) e = al(&ctx->b.epsp, 6 * V * ts);
+  if (e == hipSuccess) e = al(&ctx->b.q, 6 * V * ts);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = al(&ctx->b.sig[i], 6 * V * ts);
   for (int i = 0; i < 3 && e == hipSuccess; ++i) e = al(&ctx->b.emain[i], 6 * V * ts);
   for (int i = 0; i < 3 && e == hipSuccess; ++i) e = al(&ctx->b.enyq[i], 6 * ctx->planes * ts);
@@ -312,6 +316,8 @@ void free_all(fftevp_ctx* ctx) {
   f(ctx->b.grain2);
   f(ctx->b.estore);
   f(ctx->b.epsp0);
+  f(ctx->b.q0);
+  f(ctx->b.q);
   f(ctx->b.spin);
   for (auto p : ctx->b.tw) f(p);
   f(ctx->partial);
@@ -340,8 +346,8 @@ hipError_t mr_params(fftevp_ctx* ctx) {
 
 template <typename T, int MODE>
 hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, const void* lam,
-                             void* sig_out, const void* epsp, const void* rho, const void* sig_t,
-                             const Mat& m, C0 c0, const FinArgs& fin, const double* dE) {
+                             void* sig_out, const void* qoff, const void* rho, const void* sig_t,
+                             const Mat& m, C0 c0, const FinArgs& fin, const double* dE, const double* E0) {
   using C = cx<T>;
   LocalArgs<T> la{};
   la.e_main = (const C*)ctx->b.emain[in_buf];
@@ -350,7 +356,8 @@ hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, co
   la.e_nyq_next = (T*)ctx->b.enyq[out_buf];
   la.lam = (const T*)lam;
   la.sig = (T*)sig_out;
-  la.epsp = (const T*)epsp;
+  la.q = (const T*)qoff;
+  la.zero_in = i == 0 ? 1 : 0;  // the first iterate's strain change is the uniform dE
   la.rho = (const T*)rho;
   la.quat = (const T*)ctx->b.quat;
   la.sig_t = (const T*)sig_t;
@@ -394,6 +401,7 @@ hipError_t enqueue_iteration(fftevp_ctx* ctx, int i, int in_buf, int out_buf, co
   za.ci_d = m.ci_d;
   za.ci_o = m.ci_o;
   za.ci_s = m.ci_s;
+  for (int k = 0; k < 6; ++k) za.E0[k] = E0[k];
   e = timed(ctx, 3, i, [&] { return launch_zgamma<T>(ctx->n2, za, ctx->stream); });
   if (e != hipSuccess) return e;
   YArgs<T> yi{};
@@ -410,16 +418,17 @@ struct SolveOut {
   Ctl ctl{};
 };
 
-// Fixed-point loop on the device. Strain buffers: iteration i reads
-// in(i) = (i == 0 ? ec : w[(i - 1) % 2]) and writes out(i) = w[i % 2].
-// Returns the iteration index that converged in out.iters (count).
+// Fixed-point loop on the device over the increment's strain change de.
+// Iteration 0 starts from the uniform dE (no spectrum read); iteration i > 0
+// reads in(i) = w[(i - 1) % 2] and every iteration writes out(i) = w[i % 2],
+// the two strain buffers other than the committed one. E0: mean strain at
+// the start of the increment, E_start: the first guess of its end.
+// Afterwards e_last is the buffer holding the strain change of the latest
+// completed iteration, or -1 when that is the uniform dE (converged at once).
 template <typename T, int MODE>
 fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0 c0, FinArgs& fin,
-                         const double* E_start, const double* dE, const void* lam0, const void* epsp,
-                         const void* rho, const void* sig_t, SolveOut& out, int start_buf = -1) {
-  // the first iteration reads the strain in start_buf (default: the committed
-  // buffer); the iterations write only the two buffers other than the committed one
-  if (start_buf < 0) start_buf = ctx->ec;
+                         const double* E0, const double* E_start, const double* dE, const void* lam0,
+                         const void* qoff, const void* rho, const void* sig_t, SolveOut& out) {
   Ctl h{};
   for (int k = 0; k < 6; ++k) h.E[k] = E_start[k];
   *ctx->ctl_h = h;
@@ -430,11 +439,11 @@ fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0
   while (launched < o.max_iter) {
     const int upto = std::min(o.max_iter, launched + chunk);
     for (int i = launched; i < upto; ++i) {
-      const int in = i == 0 ? start_buf : w[(i - 1) % 2];
+      const int in = i == 0 ? w[1] : w[(i - 1) % 2];  // not read at i = 0
       const int ob = w[i % 2];
       const void* lam = i == 0 ? lam0 : ctx->b.sig[ctx->sw];
-      HIPCHK((enqueue_iteration<T, MODE>(ctx, i, in, ob, lam, ctx->b.sig[ctx->sw], epsp, rho, sig_t, m,
-                                          c0, fin, dE)));
+      HIPCHK((enqueue_iteration<T, MODE>(ctx, i, in, ob, lam, ctx->b.sig[ctx->sw], qoff, rho, sig_t, m,
+                                          c0, fin, dE, E0)));
     }
     launched = upto;
     HIPCHK(hipMemcpyAsync(ctx->ctl_h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
@@ -447,8 +456,7 @@ fftevp_status solve_loop(fftevp_ctx* ctx, const fftevp_opts& o, const Mat& m, C0
   out.iters = out.ctl.iters;
   out.done = out.ctl.done;
   const int k = out.iters - 1;
-  // buffer holding the strain of the latest completed iteration
-  if (out.done == 1) ctx->e_last = k == 0 ? start_buf : w[(k - 1) % 2];
+  if (out.done == 1) ctx->e_last = k == 0 ? -1 : w[(k - 1) % 2];
   else ctx->e_last = w[k % 2];
   return FFTEVP_OK;
 }
@@ -475,20 +483,56 @@ fftevp_opts resolve_opts(const fftevp_ctx* ctx, const fftevp_opts* in) {
   return o;
 }
 
-// Local rotation of the committed increment (axial vector per voxel, FP64,
-// into b.spin): the strain change e_new - e_old of the x-half-spectra, then
-// the forward y pass (without the reduction row), the z pass that maps each
-// compatible mode to its rotation, the inverse y pass and the inverse real
-// x-FFT of the export path (x-Nyquist plane zero). Uses the polarisation
-// buffer and the third strain buffer, both free between increments.
+// Real-space strain change of an increment from its x-half-spectrum (buffer
+// de_buf), Mandel components in T, into the polarisation buffer (free
+// between increments), for the end-of-increment update.
 template <typename T>
-hipError_t local_spin(fftevp_ctx* ctx, int e_new, int e_old) {
+hipError_t export_de(fftevp_ctx* ctx, int de_buf) {
   using C = cx<T>;
-  hipError_t e = launch_cdiff<T>((const C*)ctx->b.emain[e_new], (const C*)ctx->b.emain[e_old], (C*)ctx->b.tmain,
-                                 3 * ctx->V, ctx->stream);
+  LocalArgs<T> la{};
+  la.e_main = (const C*)ctx->b.emain[de_buf];
+  la.e_nyq = (const T*)ctx->b.enyq[de_buf];
+  la.tw = (const C*)ctx->b.tw[0];
+  la.out_t = (T*)ctx->b.tmain;
+  la.n1 = ctx->n1;
+  la.n2 = ctx->n2;
+  return launch_local<T, MODE_EXPORT>(ctx->n0, la, ctx->stream);
+}
+
+// dst = a + b for the x-half-spectra and the x-Nyquist planes of strain buffers
+template <typename T>
+hipError_t add_strain(fftevp_ctx* ctx, int dst, int a, int b) {
+  using C = cx<T>;
+  hipError_t e = launch_cadd<T>((const C*)ctx->b.emain[a], (const C*)ctx->b.emain[b], (C*)ctx->b.emain[dst],
+                                3 * ctx->V, ctx->stream);
   if (e != hipSuccess) return e;
+  return launch_cadd<T>((const C*)ctx->b.enyq[a], (const C*)ctx->b.enyq[b], (C*)ctx->b.enyq[dst],
+                        3 * ctx->planes, ctx->stream);
+}
+
+// tmain = emain[a] + emain[b], enyq[nyq_dst] = enyq[a] + enyq[b]
+template <typename T>
+hipError_t add_strain_to(fftevp_ctx* ctx, int a, int b, int nyq_dst) {
+  using C = cx<T>;
+  hipError_t e = launch_cadd<T>((const C*)ctx->b.emain[a], (const C*)ctx->b.emain[b], (C*)ctx->b.tmain,
+                                3 * ctx->V, ctx->stream);
+  if (e != hipSuccess) return e;
+  return launch_cadd<T>((const C*)ctx->b.enyq[a], (const C*)ctx->b.enyq[b], (C*)ctx->b.enyq[nyq_dst],
+                        3 * ctx->planes, ctx->stream);
+}
+
+// Local rotation of the committed increment (axial vector per voxel, FP64,
+// into b.spin) from its strain change (the x-half-spectra in de_buf): the
+// forward y pass (without the reduction row) into the polarisation buffer,
+// the z pass that maps each compatible mode to its rotation, the inverse y
+// pass and the inverse real x-FFT of the export path (x-Nyquist plane zero,
+// in the third strain buffer). Uses buffers free between increments.
+template <typename T>
+hipError_t local_spin(fftevp_ctx* ctx, int de_buf) {
+  using C = cx<T>;
+  hipError_t e = hipSuccess;
   YArgs<T> ya{};
-  ya.src = (const C*)ctx->b.tmain;
+  ya.src = (const C*)ctx->b.emain[de_buf];
   ya.dst = (C*)ctx->b.tmain;
   ya.tw = (const C*)ctx->b.tw[1];
   ya.h = ctx->n0 / 2;
@@ -505,8 +549,9 @@ hipError_t local_spin(fftevp_ctx* ctx, int e_new, int e_old) {
   za.inv_ntot = 1.0 / ((double)ctx->n1 * ctx->n2);  // the y and z round trips are unnormalised
   if ((e = launch_zspin<T>(ctx->n2, za, ctx->stream)) != hipSuccess) return e;
   ya.no_reduce = 0;
+  ya.src = (const C*)ctx->b.tmain;
   if ((e = launch_ypass<T, true>(ctx->n1, ctx->n2, ya, ctx->stream)) != hipSuccess) return e;
-  const int third = 3 - e_new - e_old;
+  const int third = 3 - ctx->ec - de_buf;
   if ((e = launch_fill<T>((T*)ctx->b.enyq[third], 6 * ctx->planes, T(0), ctx->stream)) != hipSuccess) return e;
   LocalArgs<T> la{};
   la.e_main = (const C*)ctx->b.tmain;
@@ -533,9 +578,8 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     dE[k] = E1[k] - ctx->E[k];
   }
   SolveOut so;
-  const int ec_start = ctx->ec;
-  fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, E1, dE, ctx->b.sig[ctx->sc],
-                                                ctx->b.epsp, ctx->b.rho, nullptr, so);
+  fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, ctx->E, E1, dE, ctx->b.sig[ctx->sc],
+                                                ctx->b.q, ctx->b.rho, nullptr, so);
   if (st != FFTEVP_OK) return st;
   ctx->last_iters = so.iters;
   fftevp_status ret = FFTEVP_OK;
@@ -547,17 +591,16 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     ret = FFTEVP_NOT_CONVERGED;
     ctx->err = "max_iter reached";
   } else {
-    // commit: strain, stress, macroscopic strain, then the state update
-    const int k = so.iters - 1;
-    if (k == 0) {
-      HIPCHK(launch_shift_dc<T>((cx<T>*)ctx->b.emain[ctx->ec], ctx->planes, ctx->n0 / 2, dE, ctx->stream));
-    } else {
-      ctx->ec = ctx->e_last;
-    }
-    ctx->e_last = ctx->ec;
+    // commit: stress, macroscopic strain, the state update (plastic strain,
+    // offset q += de - dt epsdot_p, densities), then the strain e_t + de
+    const int de_buf = ctx->e_last;  // -1: de is the uniform dE (converged at once)
+    if (de_buf >= 0) HIPCHK(export_de<T>(ctx, de_buf));
     std::swap(ctx->sc, ctx->sw);
     for (int q = 0; q < 6; ++q) ctx->E[q] = so.ctl.E[q];
     StateArgs<T> sa{};
+    sa.q = (T*)ctx->b.q;
+    sa.de = de_buf >= 0 ? (const T*)ctx->b.tmain : nullptr;
+    for (int q = 0; q < 6; ++q) sa.dEu[q] = dE[q];
     sa.sig = (const T*)ctx->b.sig[ctx->sc];
     sa.quat = (const T*)ctx->b.quat;
     sa.epsp = (T*)ctx->b.epsp;
@@ -610,14 +653,18 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
     // uses the orientation they acted in
     // plus the local rotation of the strain change (none when the first
     // iterate converged: the change is then the uniform dE)
-    const bool spin = ctx->rot_on && ctx->ec != ec_start;
-    if (spin) HIPCHK(timed(ctx, 1, -1, [&] { return local_spin<T>(ctx, ctx->ec, ec_start); }));
+    const bool spin = ctx->rot_on && de_buf >= 0;
+    if (spin) HIPCHK(timed(ctx, 1, -1, [&] { return local_spin<T>(ctx, de_buf); }));
     if (ctx->rot_on)
       HIPCHK(timed(ctx, 1, -1, [&] { return launch_rotate<T>((T*)ctx->b.quat, (const T*)ctx->b.gd,
                                                               spin ? ctx->b.spin : nullptr, ctx->V, dt,
                                                               ctx->stream); }));
     // the next increment's frozen parameters of the paper's law
     if (ctx->law == 1) HIPCHK(mr_params(ctx));
+    // committed strain e_t + de
+    if (de_buf >= 0) HIPCHK(add_strain<T>(ctx, ctx->ec, ctx->ec, de_buf));
+    else HIPCHK(launch_shift_dc<T>((cx<T>*)ctx->b.emain[ctx->ec], ctx->planes, ctx->n0 / 2, dE, ctx->stream));
+    ctx->e_last = ctx->ec;
     HIPCHK(hipMemcpyAsync(ctx->red2_h, ctx->red2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->prof) HIPCHK(harvest(ctx, 0, false));
@@ -645,7 +692,7 @@ fftevp_status step_impl(fftevp_ctx* ctx, const fftevp_opts& o, fftevp_report* re
   return ret;
 }
 
-size_t snap_layout(const fftevp_ctx* c, size_t off[9]);
+size_t snap_layout(const fftevp_ctx* c, size_t off[kSnapParts]);
 
 // Stress redistribution (Sec. 2.5): the last increment's solve repeated from
 // the mechanical state of the snapshot taken before it (plastic strain,
@@ -668,11 +715,12 @@ fftevp_status redistribute_impl(fftevp_ctx* ctx, const fftevp_opts& o, const voi
   const double dt = ctx->load.dt;
   if (!(std::fabs(hdr[11] + dt - ctx->t) <= 1e-9 * std::max(dt, ctx->t)))
     return fail(ctx, FFTEVP_EINVAL, "the snapshot must be the state one increment before the current one");
-  size_t off[9];
+  size_t off[kSnapParts];
   snap_layout(ctx, off);
   const size_t V = ctx->V, ts = sizeof(T);
   const char* s = (const char*)before;
   HIPCHK(hipMemcpyAsync(ctx->b.epsp0, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.q0, s + off[9], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.sig[ctx->sw], s + off[2], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.emain[3], s + off[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.enyq[3], s + off[4], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice, ctx->stream));
@@ -688,8 +736,8 @@ fftevp_status redistribute_impl(fftevp_ctx* ctx, const fftevp_opts& o, const voi
     dE[k] = E1[k] - E0[k];
   }
   SolveOut so;
-  fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, E1, dE, ctx->b.sig[ctx->sw], ctx->b.epsp0,
-                                                ctx->b.rho, nullptr, so, 3);
+  fftevp_status st = solve_loop<T, MODE_NEWTON>(ctx, o, m, c0, fin, E0, E1, dE, ctx->b.sig[ctx->sw],
+                                                ctx->b.q0, ctx->b.rho, nullptr, so);
   if (st != FFTEVP_OK) return st;
   fftevp_status ret = FFTEVP_OK;
   double rho_mean = 0.0;
@@ -698,23 +746,32 @@ fftevp_status redistribute_impl(fftevp_ctx* ctx, const fftevp_opts& o, const voi
   } else if (so.done != 1) {
     ret = fail(ctx, FFTEVP_NOT_CONVERGED, "max_iter reached");
   } else {
-    if (so.iters == 1) {
-      // converged at the first iterate: its strain is the start state plus dE,
-      // moved into a buffer of the committed rotation
-      const int w0 = (ctx->ec + 1) % 3;
-      HIPCHK(hipMemcpyAsync(ctx->b.emain[w0], ctx->b.emain[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
-      HIPCHK(hipMemcpyAsync(ctx->b.enyq[w0], ctx->b.enyq[3], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
-                            ctx->stream));
-      HIPCHK(launch_shift_dc<T>((cx<T>*)ctx->b.emain[w0], ctx->planes, ctx->n0 / 2, dE, ctx->stream));
-      ctx->ec = w0;
+    // new strain: the snapshot's plus the strain change, in a buffer of the
+    // committed rotation (the one holding the change, or a free one when the
+    // change is the uniform dE); the real change first, for the state update
+    const int de_buf = ctx->e_last;
+    int newec;
+    if (de_buf >= 0) {
+      HIPCHK(export_de<T>(ctx, de_buf));
+      HIPCHK(add_strain<T>(ctx, de_buf, de_buf, 3));
+      newec = de_buf;
     } else {
-      ctx->ec = ctx->e_last;
+      newec = (ctx->ec + 1) % 3;
+      HIPCHK(hipMemcpyAsync(ctx->b.emain[newec], ctx->b.emain[3], 6 * V * ts, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->b.enyq[newec], ctx->b.enyq[3], 6 * ctx->planes * ts, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+      HIPCHK(launch_shift_dc<T>((cx<T>*)ctx->b.emain[newec], ctx->planes, ctx->n0 / 2, dE, ctx->stream));
     }
-    ctx->e_last = ctx->ec;
+    ctx->ec = ctx->e_last = newec;
     std::swap(ctx->sc, ctx->sw);
     for (int q = 0; q < 6; ++q) ctx->E[q] = so.ctl.E[q];
     HIPCHK(hipMemcpyAsync(ctx->b.epsp, ctx->b.epsp0, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->b.q, ctx->b.q0, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
     StateArgs<T> sa{};
+    sa.q = (T*)ctx->b.q;
+    sa.de = de_buf >= 0 ? (const T*)ctx->b.tmain : nullptr;
+    for (int q = 0; q < 6; ++q) sa.dEu[q] = dE[q];
     sa.sig = (const T*)ctx->b.sig[ctx->sc];
     sa.quat = (const T*)ctx->b.quat;
     sa.epsp = (T*)ctx->b.epsp;
@@ -760,7 +817,7 @@ fftevp_status redistribute_impl(fftevp_ctx* ctx, const fftevp_opts& o, const voi
   return ret;
 }
 
-size_t snap_layout(const fftevp_ctx* c, size_t off[9]) {
+size_t snap_layout(const fftevp_ctx* c, size_t off[kSnapParts]) {
   const size_t ts = c->tsize, V = c->V;
   size_t o = kHeader * sizeof(double);
   off[0] = o;  // epsp
@@ -782,6 +839,8 @@ size_t snap_layout(const fftevp_ctx* c, size_t off[9]) {
   if (c->drx_on) o += V * ts + ((V * sizeof(int) + 255) & ~(size_t)255);
   off[8] = o;  // orientations when the lattice rotates, [4][V]
   if (c->rot_on) o += 4 * V * ts;
+  off[9] = o;  // offset q = e - epsp, [6][V]
+  o += 6 * V * ts;
   return o;
 }
 
@@ -810,7 +869,7 @@ fftevp_status adjoint_impl(fftevp_ctx* ctx, const fftevp_opts& o, const void* be
   if (st != FFTEVP_OK) return st;
   if ((st = check_snapshot(ctx, after)) != FFTEVP_OK) return st;
   const size_t V = ctx->V, ts = sizeof(T);
-  size_t off[9];
+  size_t off[kSnapParts];
   snap_layout(ctx, off);
   // the adjoint solve reuses the forward state buffers (a snapshot must be
   // loaded afterwards): the eigenstrain of the adjoint problem goes into the
@@ -864,7 +923,8 @@ fftevp_status adjoint_impl(fftevp_ctx* ctx, const fftevp_opts& o, const void* be
     SolveOut so;
     const int keep = ctx->last_iters;
     ctx->last_iters = ctx->adj_iters;
-    st = solve_loop<T, MODE_TANGENT>(ctx, o, m, c0, fin, E0, E0, ctx->b.sig[ctx->sc], eta, aa.rho0,
+    const double zero[6] = {0, 0, 0, 0, 0, 0};
+    st = solve_loop<T, MODE_TANGENT>(ctx, o, m, c0, fin, zero, E0, E0, ctx->b.sig[ctx->sc], eta, aa.rho0,
                                      aa.sig_t, so);
     ctx->adj_iters = so.iters;
     ctx->last_iters = keep;
@@ -977,6 +1037,7 @@ fftevp_status fftevp_set_microstructure(fftevp_ctx* ctx, const double* quat, con
   // fresh mechanical state
   const size_t ts = ctx->tsize;
   HIPCHK(hipMemsetAsync(ctx->b.epsp, 0, 6 * V * ts, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->b.q, 0, 6 * V * ts, ctx->stream));
   for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(ctx->b.sig[i], 0, 6 * V * ts, ctx->stream));
   for (int i = 0; i < 3; ++i) {
     HIPCHK(hipMemsetAsync(ctx->b.emain[i], 0, 6 * V * ts, ctx->stream));
@@ -1076,6 +1137,7 @@ fftevp_status fftevp_set_drx(fftevp_ctx* ctx, const fftevp_drx* p, const double*
   if (e == hipSuccess && !ctx->b.grain2) e = hipMalloc((void**)&ctx->b.grain2, V * sizeof(int));
   // buffers of the stress redistribution (fftevp_redistribute)
   if (e == hipSuccess && !ctx->b.epsp0) e = hipMalloc(&ctx->b.epsp0, 6 * V * ctx->tsize);
+  if (e == hipSuccess && !ctx->b.q0) e = hipMalloc(&ctx->b.q0, 6 * V * ctx->tsize);
   if (e == hipSuccess && !ctx->b.emain[3]) e = hipMalloc(&ctx->b.emain[3], 6 * V * ctx->tsize);
   if (e == hipSuccess && !ctx->b.enyq[3]) e = hipMalloc(&ctx->b.enyq[3], 6 * ctx->planes * ctx->tsize);
   if (e != hipSuccess) {
@@ -1380,12 +1442,24 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
     return dbl ? launch_export<double>((const double*)src, dst, V, ncomp, mandel, ctx->stream)
                : launch_export<float>((const float*)src, dst, V, ncomp, mandel, ctx->stream);
   };
-  auto strain = [&](int buf) {
+  // strain of buffer buf; with plus >= 0 the sum of two buffers (the
+  // committed strain and an iterate's strain change), formed in the
+  // polarisation buffer and the third Nyquist plane, free between increments
+  auto strain = [&](int buf, int plus) -> hipError_t {
+    const void* mainp = ctx->b.emain[buf];
+    const void* nyqp = ctx->b.enyq[buf];
+    if (plus >= 0 && plus != buf) {
+      const int third = 3 - buf - plus;
+      hipError_t e2 = dbl ? add_strain_to<double>(ctx, buf, plus, third) : add_strain_to<float>(ctx, buf, plus, third);
+      if (e2 != hipSuccess) return e2;
+      mainp = ctx->b.tmain;
+      nyqp = ctx->b.enyq[third];
+    }
     Mat m{};
     if (dbl) {
       LocalArgs<double> la{};
-      la.e_main = (const cx<double>*)ctx->b.emain[buf];
-      la.e_nyq = (const double*)ctx->b.enyq[buf];
+      la.e_main = (const cx<double>*)mainp;
+      la.e_nyq = (const double*)nyqp;
       la.tw = (const cx<double>*)ctx->b.tw[0];
       la.out = dst;
       la.n1 = ctx->n1;
@@ -1394,8 +1468,8 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
       return launch_local<double, MODE_EXPORT>(ctx->n0, la, ctx->stream);
     }
     LocalArgs<float> la{};
-    la.e_main = (const cx<float>*)ctx->b.emain[buf];
-    la.e_nyq = (const float*)ctx->b.enyq[buf];
+    la.e_main = (const cx<float>*)mainp;
+    la.e_nyq = (const float*)nyqp;
     la.tw = (const cx<float>*)ctx->b.tw[0];
     la.out = dst;
     la.n1 = ctx->n1;
@@ -1406,11 +1480,11 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
   hipError_t e;
   switch (field) {
     case FFTEVP_FIELD_SIGMA: e = exp(ctx->b.sig[ctx->sc], 6, 1); break;
-    case FFTEVP_FIELD_STRAIN: e = strain(ctx->ec); break;
+    case FFTEVP_FIELD_STRAIN: e = strain(ctx->ec, -1); break;
     case FFTEVP_FIELD_EPS_P: e = exp(ctx->b.epsp, 6, 1); break;
     case FFTEVP_FIELD_RHO: e = exp(ctx->b.rho, 1, 0); break;
     case FFTEVP_FIELD_SIGMA_ITER: e = exp(ctx->b.sig[ctx->sw], 6, 1); break;
-    case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->e_last); break;
+    case FFTEVP_FIELD_STRAIN_ITER: e = strain(ctx->ec, ctx->e_last); break;
     case FFTEVP_FIELD_KAPPA:
       if (!ctx->drx_on) return fail(ctx, FFTEVP_ESTATE, "DRX nucleation is not enabled (fftevp_set_drx)");
       e = exp(ctx->b.kappa, 1, 0);
@@ -1465,13 +1539,13 @@ fftevp_status fftevp_get_field(fftevp_ctx* ctx, int field, double* dst) {
 
 size_t fftevp_state_bytes(const fftevp_ctx* ctx) {
   if (!ctx) return 0;
-  size_t off[9];
+  size_t off[kSnapParts];
   return snap_layout(ctx, off);
 }
 
 fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   if (!ctx || !dst) return fail(ctx, FFTEVP_EINVAL, "null argument");
-  size_t off[9];
+  size_t off[kSnapParts];
   snap_layout(ctx, off);
   const size_t ts = ctx->tsize, V = ctx->V;
   double hdr[kHeader] = {0};
@@ -1510,13 +1584,14 @@ fftevp_status fftevp_save_state(fftevp_ctx* ctx, void* dst) {
   }
   if (ctx->rot_on)
     HIPCHK(hipMemcpyAsync(d + off[8], ctx->b.quat, 4 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d + off[9], ctx->b.q, 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return FFTEVP_OK;
 }
 
 fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
   if (!ctx || !src) return fail(ctx, FFTEVP_EINVAL, "null argument");
-  size_t off[9];
+  size_t off[kSnapParts];
   snap_layout(ctx, off);
   const size_t ts = ctx->tsize, V = ctx->V;
   double hdr[kHeader];
@@ -1528,6 +1603,7 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src) {
       hdr[17] != (ctx->drx_on ? 1.0 : 0.0) || hdr[18] != (ctx->rot_on ? 1.0 : 0.0))
     return fail(ctx, FFTEVP_EINVAL, "snapshot does not match this context");
   HIPCHK(hipMemcpyAsync(ctx->b.epsp, s + off[0], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->b.q, s + off[9], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.rho, s + off[1], V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.sig[ctx->sc], s + off[2], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->b.emain[ctx->ec], s + off[3], 6 * V * ts, hipMemcpyDeviceToDevice, ctx->stream));

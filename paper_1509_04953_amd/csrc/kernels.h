@@ -51,14 +51,24 @@ struct FinArgs {
 };
 
 template <typename T>
+// The iteration works on the increment's strain change: the spectra hold
+// de = e - e_t (a compatible field of mean E - E_t), each voxel carries the
+// offset q = e_t - epsp_t, and the local right-hand side is
+// b = C0^-1 lam + de + q, the polarisation tau = sigma - C0 (de - C0^-1
+// (sigma - lam)). In exact arithmetic this is the plain iteration on e (the
+// Green operator maps C0 e_t to e_t - E_t); in floating point it never
+// subtracts the total strains (0.1-0.4 late in a path) to form the elastic
+// strain (1e-3), which in FP32 would cost five digits.
 struct LocalArgs {
-  const cx<T>* e_main;  // x-half-spectrum of e, [6][n2][n1][n0/2]
-  const T* e_nyq;       // x-Nyquist plane of e, [6][n2][n1]
+  const cx<T>* e_main;  // x-half-spectrum of de (export: of the field exported), [6][n2][n1][n0/2]
+  const T* e_nyq;       // x-Nyquist plane of de, [6][n2][n1]
   cx<T>* t_main;        // out: x-half-spectrum of tau
-  T* e_nyq_next;        // out: x-Nyquist plane of the next e
+  T* e_nyq_next;        // out: x-Nyquist plane of the next de
   const T* lam;         // multiplier (previous stress), [6][V] Mandel
   T* sig;               // out: stress, [6][V] Mandel
-  const T* epsp;        // plastic strain (tangent mode: eigenstrain), [6][V]
+  const T* q;           // strain offset of b: e_t - epsp_t (tangent mode: -eigenstrain), [6][V]
+  int zero_in;          // de is zero (the first iterate): the spectra are not read
+  T* out_t;             // export mode: Mandel components in T, [6][V] (instead of out)
   const T* rho;         // density, [V]
   const T* quat;        // orientation, [4][V]
   const T* sig_t;       // tangent mode: stress the tangent is taken at
@@ -100,6 +110,7 @@ struct ZArgs {
   int h, n1;
   double inv_n0, inv_n1, inv_n2, inv_ntot;
   double c0l, c0m, ci_d, ci_o, ci_s;
+  double E0[6];          // mean strain at the start of the increment (Mandel): the mean of de is E - E0
 };
 
 // GND update (Sec. 2.2, Eq. 7-8)
@@ -151,6 +162,9 @@ struct StateArgs {
   double* partial;  // [blocks][2]: sum rho_new, sum sum_a |gdot_a|
   T* gd;            // optional out: slip rates of the increment, [12][V] (GND update)
   int dens;         // 1: advance the densities too; 0: plastic strain only
+  T* q;             // offset e - epsp (in/out): += de - dt epsdot_p, [6][V] Mandel
+  const T* de;      // the increment's strain change, [6][V] Mandel; null: uniform dEu
+  double dEu[6];
   size_t nvox;
   double dt, gdot0, k1, k2;
   Mat m;
@@ -202,9 +216,9 @@ hipError_t launch_zgamma(int n2, const ZArgs<T>& a, hipStream_t s);
 // a.inv_ntot, inverse z-FFT; a.ctl unused
 template <typename T>
 hipError_t launch_zspin(int n2, const ZArgs<T>& a, hipStream_t s);
-// out = a - b, n complex values
+// out = a + b, n complex values (out may alias a or b)
 template <typename T>
-hipError_t launch_cdiff(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s);
+hipError_t launch_cadd(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_state(const StateArgs<T>& a, int nblocks, double* out2, hipStream_t s);
 template <typename T>

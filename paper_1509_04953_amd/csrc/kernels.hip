@@ -199,14 +199,14 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
 
   // per-voxel inputs of the thread's first voxel, requested before the x-FFT
   // so that their latency overlaps it (later voxels load in the loop)
-  T pq[4], plam[6], pep[6], prho;
+  T pq[4], plam[6], poff[6], prho;
   auto fetch = [&](size_t g) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) pq[k] = a.quat[(size_t)k * vox + g];
 #pragma unroll
     for (int k = 0; k < 6; ++k) plam[k] = a.lam[(size_t)k * vox + g];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pep[k] = a.epsp[(size_t)k * vox + g];
+    for (int k = 0; k < 6; ++k) poff[k] = a.q[(size_t)k * vox + g];
     prho = a.rho[g];
   };
   if constexpr (MODE != MODE_EXPORT) {
@@ -214,17 +214,29 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
     fetch((line0 + l) * N0 + x);
   }
 
-  load_packed<T, N0>(a.e_main, a.e_nyq, line0, sh);
-  __syncthreads();
-  fft_lines<T, N0, true, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
+  const bool zero_in = MODE != MODE_EXPORT && a.zero_in;
+  if (!zero_in) {
+    load_packed<T, N0>(a.e_main, a.e_nyq, line0, sh);
+    __syncthreads();
+    fft_lines<T, N0, true, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
+  }
 
   if constexpr (MODE == MODE_EXPORT) {
-    // write the real strain, plain components, FP64
+    // write the real field: plain components in FP64, or Mandel in T
 #pragma unroll
     for (int v = 0; v < S::VPT; ++v) {
       const int t = threadIdx.x + v * S::NT;
       const int l = t / N0, x = t - (t / N0) * N0;
       const size_t g = (line0 + l) * N0 + x;
+      if (a.out_t) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
+          a.out_t[(size_t)(2 * p) * vox + g] = z.x;
+          a.out_t[(size_t)(2 * p + 1) * vox + g] = z.y;
+        }
+        continue;
+      }
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
@@ -251,11 +263,16 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
     const int l = t / N0, x = t - (t / N0) * N0;
     const size_t g = (line0 + l) * N0 + x;
     auto load_e = [&](T (&e)[6]) {
+      if (zero_in) {
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
-        e[2 * p] = z.x;
-        e[2 * p + 1] = z.y;
+        for (int k = 0; k < 6; ++k) e[k] = T(0);
+      } else {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const cx<T> z = sh[(p * S::LPB + l) * S::LS + x];
+          e[2 * p] = z.x;
+          e[2 * p + 1] = z.y;
+        }
       }
       if (a.add_dE) {
 #pragma unroll
@@ -266,7 +283,7 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
     const T tauc = T(M.tau0) + T(M.taylor) * sqrt(prho);
     const T itauc = T(1) / tauc;
 
-    // b = C0^-1 lam + e - epsp in the crystal frame; start from lam
+    // b = C0^-1 lam + de + q in the crystal frame; start from lam
     T b[6], sc[6];
     {
       T R[9], e[6], bs[6];
@@ -274,7 +291,7 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
       load_e(e);
       cubic_mul(ci_d, ci_o, ci_s, plam, bs);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) bs[k] += e[k] - pep[k];
+      for (int k = 0; k < 6; ++k) bs[k] += e[k] + poff[k];
       to_crystal(R, bs, b);
       if constexpr (MODE == MODE_NEWTON) to_crystal(R, plam, sc);
     }
@@ -375,7 +392,7 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
       nit = 1;
     }
 
-    // back to the sample frame; eps = e - C0^-1 (sigma - lam); tau = sigma - C0 eps
+    // back to the sample frame; eps - e_t = de - C0^-1 (sigma - lam); tau = sigma - C0 (eps - e_t)
     T sig[6], err[6], e[6];
     {
       T R[9], dsl[6];
@@ -694,7 +711,7 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zgamma(ZArgs<T> a) {
     __syncthreads();
     if (threadIdx.x == 0) {
       finalize_sums(a.fin, a.ctl, tot);
-      for (int k = 0; k < 6; ++k) E_sh[k] = a.ctl->E[k];
+      for (int k = 0; k < 6; ++k) E_sh[k] = a.ctl->E[k] - a.E0[k];
     }
     __syncthreads();
   }
@@ -806,11 +823,10 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zspin(ZArgs<T> a) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cdiff(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
-                                               cx<T>* __restrict__ out, size_t n) {
+__global__ __launch_bounds__(256) void k_cadd(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const cx<T> x = a[i], y = b[i];
-    out[i] = {x.x - y.x, x.y - y.y};
+    out[i] = {x.x + y.x, x.y + y.y};
   }
 }
 
@@ -872,7 +888,11 @@ __global__ __launch_bounds__(256) void k_state(StateArgs<T> a) {
     double dpc[6], dp[6];
     for (int k = 0; k < 6; ++k) dpc[k] = a.gdot0 * (k < 3 ? kUN : kUS) * gk[k];
     to_sample(R, dpc, dp);
-    for (int k = 0; k < 6; ++k) a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
+    for (int k = 0; k < 6; ++k) {
+      a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
+      const double dek = a.de ? (double)a.de[k * V + g] : a.dEu[k];
+      a.q[k * V + g] = (T)((double)a.q[k * V + g] + dek - a.dt * dp[k]);
+    }
     const double rn = a.dens ? rho + a.dt * (a.k1 * sqrt(rho) - a.k2 * rho) * a.gdot0 * asum : rho;
     if (a.dens) a.rho[g] = (T)rn;
     if (a.gd) {
@@ -1209,7 +1229,11 @@ __global__ __launch_bounds__(256) void k_state_mr(StateArgs<T> a) {
       ep2 += dpc[k] * dpc[k];
     }
     to_sample(R, dpc, dp);
-    for (int k = 0; k < 6; ++k) a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
+    for (int k = 0; k < 6; ++k) {
+      a.epsp[k * V + g] = (T)((double)a.epsp[k * V + g] + a.dt * dp[k]);
+      const double dek = a.de ? (double)a.de[k * V + g] : a.dEu[k];
+      a.q[k * V + g] = (T)((double)a.q[k * V + g] + dek - a.dt * dp[k]);
+    }
     // von Mises stress and equivalent plastic rate (frame invariant)
     const double tr = (sc[0] + sc[1] + sc[2]) / 3.0;
     double s2 = 0.0;
@@ -1457,7 +1481,7 @@ __global__ __launch_bounds__(256) void k_adj_setup(AdjArgs<T> a) {
     to_sample(R, ec, es);
     double n2 = 0.0;
     for (int k = 0; k < 6; ++k) {
-      a.eta[k * V + g] = (T)es[k];
+      a.eta[k * V + g] = (T)(-es[k]);  // the tangent solve takes the offset q = -eta
       n2 += es[k] * es[k];
     }
     part[0] += n2;
@@ -1706,8 +1730,8 @@ hipError_t launch_zspin(int n2, const ZArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_cdiff(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cdiff<T>, dim3(grid_for(n)), dim3(256), 0, s, a, b, out, n);
+hipError_t launch_cadd(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cadd<T>, dim3(grid_for(n)), dim3(256), 0, s, a, b, out, n);
   return hipGetLastError();
 }
 
@@ -1857,7 +1881,7 @@ hipError_t launch_fill(T* p, size_t n, T v, hipStream_t s) {
   template hipError_t launch_rho_tot<T>(const DrxArgs<T>&, bool, double, double*, hipStream_t); \
   template hipError_t launch_rotate<T>(T*, const T*, const double*, size_t, double, hipStream_t); \
   template hipError_t launch_zspin<T>(int, const ZArgs<T>&, hipStream_t);                      \
-  template hipError_t launch_cdiff<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t); \
+  template hipError_t launch_cadd<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t); \
   template hipError_t launch_sweep<T>(const DrxArgs<T>&, int, double*, hipStream_t);          \
   template hipError_t launch_mr_params<T>(const T*, const T*, const T*, T*, size_t, const MrConst&, \
                                           hipStream_t);                                       \

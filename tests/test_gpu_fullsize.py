@@ -170,34 +170,50 @@ def test_curve_64cube_matches_golden(require_gpu):
 
 
 def test_mixed_vs_fp64_128(require_gpu):
-    """128^3, 500 grains (the mixed-precision configuration): per-field
-    relative L2 difference of the mixed path from the FP64 path over ten
-    increments at the same stop rule (the FP64 path is the oracle's to 1e-10
-    wherever the oracle can run)."""
+    """128^3, 500 grains, the whole path of the mixed-precision configuration
+    (100 increments to 20 % strain): per-field relative L2 errors of the
+    mixed path and of the FP64 path, both at the workload's stop rule
+    (tol 1e-6), against the FP64 path converged to tol 1e-10 (the oracle's
+    solution to 1e-10 wherever the oracle can run). Each path stops once its
+    strain mismatch is below tol |E|, which leaves the stress field off the
+    converged one by more than that (the stop rule's own error, the FP64
+    column); FP32 rounding adds little to it. Bound for the mixed stress
+    field: 1e-5, and within 1.5x of the FP64 path at the same stop rule."""
     from paper_1509_04953_amd import Opts
     w = synth.workload("cu128")
     s, _, _ = make(w, "mixed")
     s64, _, _ = make(w, "fp64")
-    cg, c64 = [], []
-    for inc in range(10):
-        print(f"case: mixed vs fp64 128^3 increment {inc}", flush=True)
+    sref, _, _ = make(w, "fp64")
+    cg, c64, cref = [], [], []
+    for inc in range(w.increments):
+        if inc % 10 == 0:
+            print(f"case: mixed vs fp64 128^3 increment {inc}", flush=True)
         r = s.step(Opts(tol=w.tol))
         r64 = s64.step(Opts(tol=w.tol))
-        assert r.status == 0 and r64.status == 0
+        rr = sref.step(Opts(tol=1e-10, max_iter=5000))
+        assert r.status == 0 and r64.status == 0 and rr.status == 0
         cg.append(r.Sigma[2])
         c64.append(r64.Sigma[2])
-    errs = {}
+        cref.append(rr.Sigma[2])
+    errs, errs64 = {}, {}
     for k in ("sigma", "strain", "epsp", "rho"):
-        v = s64.field(k).cpu().numpy()
-        errs[k] = float(np.linalg.norm(s.field(k).cpu().numpy() - v) / np.linalg.norm(v))
-    errs["curve"] = float(np.abs(np.array(cg) - np.array(c64)).max() / np.abs(np.array(c64)).max())
-    print("128^3 mixed vs fp64 relative errors:", json.dumps(errs), flush=True)
-    # each path stops once its strain mismatch is below tol |E|; the stress
-    # field then differs by up to about C tol |E| / |sigma| ~ 20 tol here
-    # (measured 9.8e-6), the strain and the curve by far less
-    assert errs["curve"] < 1e-5 and errs["strain"] < 1e-5
-    assert errs["sigma"] < 5e-5
+        v = sref.field(k).cpu().numpy()
+        nv = np.linalg.norm(v)
+        errs[k] = float(np.linalg.norm(s.field(k).cpu().numpy() - v) / nv)
+        errs64[k] = float(np.linalg.norm(s64.field(k).cpu().numpy() - v) / nv)
+    cr = np.array(cref)
+    errs["curve"] = float(np.abs(np.array(cg) - cr).max() / np.abs(cr).max())
+    errs64["curve"] = float(np.abs(np.array(c64) - cr).max() / np.abs(cr).max())
+    print("128^3, 100 increments, errors against FP64 at tol 1e-10: mixed", json.dumps(errs),
+          "fp64 at tol 1e-6", json.dumps(errs64), flush=True)
+    assert errs["sigma"] < 1e-5 and errs["curve"] < 1e-5 and errs["strain"] < 1e-5
     assert errs["epsp"] < 1e-4 and errs["rho"] < 1e-4
+    # the iteration works on the increment's strain change and a per-voxel
+    # offset e_t - epsp_t, so FP32 never forms the elastic strain from two
+    # total strains: the mixed errors are those of the stop rule itself
+    # (measured 2.97e-6 against 2.74e-6 for the stress)
+    for k in ("sigma", "strain", "epsp", "curve"):
+        assert errs[k] < 1.5 * errs64[k] + 5e-7, (k, errs[k], errs64[k])
 
 
 def test_64cube_fifty_increments_properties(require_gpu):
