@@ -184,17 +184,145 @@ __device__ __forceinline__ void stockham_stage(cx<T>* __restrict__ buf,
   __syncthreads();
 }
 
-template <typename T, int N, int NS, bool INV, int LINES, int LS, int NT>
-__device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw) {
-  if constexpr (NS < N) {
-    // radix plan: 16 where it leaves a factor of at least 8 (or is the whole
-    // transform), else 8s, then a final 4 or 2:
-    // 16 -> 16, 32 -> 8x4, 64 -> 8x8, 128 -> 16x8, 256 -> 16x16, 512 -> 8x8x8
-    constexpr int REM = N / NS;
-    constexpr int R = (REM == 16 || REM == 128 || REM == 256) ? 16
-                      : (REM % 8 == 0 ? 8 : (REM % 4 == 0 ? 4 : 2));
+// radix plan: 16 where it leaves a factor of at least 8 (or is the whole
+// transform), else 8s, then a final 4 or 2:
+// 16 -> 16, 32 -> 8x4, 64 -> 8x8, 128 -> 16x8, 256 -> 16x16, 512 -> 8x8x8
+__host__ __device__ constexpr int radix_at(int n, int ns) {
+  const int rem = n / ns;
+  return (rem == 16 || rem == 128 || rem == 256) ? 16 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2));
+}
+// NS of the plan's last stage (1 for a one-stage plan)
+__host__ __device__ constexpr int last_stage_ns(int n) {
+  int ns = 1;
+  while (ns * radix_at(n, ns) < n) ns *= radix_at(n, ns);
+  return ns;
+}
+
+// the stages of the plan from NS up to (not including) the one at STOP
+template <typename T, int N, int NS, int STOP, bool INV, int LINES, int LS, int NT>
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* tw) {
+  if constexpr (NS < STOP) {
+    constexpr int R = radix_at(N, NS);
     stockham_stage<T, N, R, NS, INV, LINES, LS, NT>(buf, tw);
-    fft_rest<T, N, NS * R, INV, LINES, LS, NT>(buf, tw);
+    fft_stages<T, N, NS * R, STOP, INV, LINES, LS, NT>(buf, tw);
+  }
+}
+
+// P complex values of row `row` at column w (P = 2: one 16-byte FP32 access)
+template <typename T, int P>
+__device__ __forceinline__ void load_row(const cx<T>* __restrict__ p, cx<T> (&o)[P]) {
+  if constexpr (P == 2) {
+    static_assert(sizeof(T) == 4, "pairs are FP32");
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    o[0] = {f.x, f.y};
+    o[1] = {f.z, f.w};
+  } else {
+    o[0] = p[0];
+  }
+}
+template <typename T, int P>
+__device__ __forceinline__ void store_row(cx<T>* __restrict__ p, const cx<T> (&o)[P]) {
+  if constexpr (P == 2) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+  } else {
+    p[0] = o[0];
+  }
+}
+
+// First stage of the plan (NS = 1, no twiddles) read straight from global
+// rows: row i of a tile holds element i of its W lines (row stride rs, W
+// contiguous complex values, P lines per thread). Thread (column w, butterfly
+// j) loads rows j + r N/R, applies the radix-R DFT and writes the outputs to
+// LDS line w at j R + r (line stride LS). Consecutive threads take
+// neighbouring columns, so each load covers whole rows. Ends with a barrier.
+template <typename T, int N, int W, bool INV, int LS, int NT, int P>
+__device__ __forceinline__ void first_stage_from_rows(const cx<T>* __restrict__ src, size_t rs,
+                                                      cx<T>* sh) {
+  constexpr int R = radix_at(N, 1);
+  constexpr int BF = N / R;
+  constexpr int WP = W / P;
+  constexpr int TOTAL = WP * BF;
+  constexpr int PER = (TOTAL + NT - 1) / NT;
+  static_assert(W % P == 0, "whole pairs");
+  cx<T> v[PER][P][R];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if ((TOTAL % NT) == 0 || idx < TOTAL) {
+      const int w = (idx % WP) * P, j = idx / WP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cx<T> o[P];
+        load_row<T, P>(src + (size_t)(j + r * BF) * rs + w, o);
+#pragma unroll
+        for (int p = 0; p < P; ++p) v[b][p][r] = o[p];
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if ((TOTAL % NT) == 0 || idx < TOTAL) {
+      const int w = (idx % WP) * P, j = idx / WP;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        dftR<T, R, INV>(v[b][p]);
+        cx<T>* dst = sh + (w + p) * LS + j * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r] = v[b][p][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Last stage of the plan (NS = N / R) written straight to global rows:
+// thread (column w, butterfly j) reads inputs j + r NS of LDS line w,
+// applies the twiddles and the radix-R DFT and stores output r (element
+// j + r NS) to that row. The stage before must have ended with a barrier. A
+// one-stage plan (NS = 1) makes this the whole transform.
+template <typename T, int N, int W, bool INV, int LS, int NT, int P>
+__device__ __forceinline__ void last_stage_to_rows(const cx<T>* sh, const cx<T>* __restrict__ tw,
+                                                   cx<T>* __restrict__ dst, size_t rs) {
+  constexpr int NSL = last_stage_ns(N);
+  constexpr int R = N / NSL;
+  constexpr int WP = W / P;
+  constexpr int TOTAL = WP * NSL;
+  constexpr int PER = (TOTAL + NT - 1) / NT;
+  static_assert(W % P == 0, "whole pairs");
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if ((TOTAL % NT) == 0 || idx < TOTAL) {
+      const int w = (idx % WP) * P, j = idx / WP;
+      cx<T> v[P][R];
+      cx<T> wt[R > 1 && NSL > 1 ? R - 1 : 1];
+      if constexpr (NSL > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) wt[r - 1] = tw[j * r];
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[p][r] = sh[(w + p) * LS + j + r * NSL];
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if constexpr (NSL > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r)
+            v[p][r] = INV ? cmulc(v[p][r], wt[r - 1]) : cmul(v[p][r], wt[r - 1]);
+        }
+        dftR<T, R, INV>(v[p]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cx<T> o[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) o[p] = v[p][r];
+        store_row<T, P>(dst + (size_t)(j + r * NSL) * rs + w, o);
+      }
+    }
   }
 }
 
@@ -202,7 +330,7 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw) {
 // Must be called by all NT threads of the block; ends with a barrier.
 template <typename T, int N, bool INV, int LINES, int LS, int NT>
 __device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* __restrict__ tw) {
-  fft_rest<T, N, 1, INV, LINES, LS, NT>(buf, tw);
+  fft_stages<T, N, 1, N, INV, LINES, LS, NT>(buf, tw);
 }
 
 }  // namespace fftevp

@@ -616,6 +616,55 @@ __device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict
   }
 }
 
+// Transforms of a tile's W lines between global rows and LDS. With FUSE the
+// first stage of the plan reads the rows itself and the last one writes
+// them, so a two-stage line (32 to 256 points) passes through LDS once
+// instead of three times, with one barrier instead of five. The z pass
+// (forward, Green operator, inverse in one block) gained 4-11 % from it at
+// 128^3 and 256^3 and the y passes 2-8 % on lines of 128 points; on lines of
+// 256 points the y passes ran 5-11 % slower (fewer threads issue the row
+// accesses), so they keep the row copies there.
+#ifndef FFTEVP_FUSED_EDGE
+#define FFTEVP_FUSED_EDGE 1
+#endif
+#ifndef FFTEVP_FUSED_Y_MAX
+#define FFTEVP_FUSED_Y_MAX 128
+#endif
+// lines per thread at the edges: FP32 pairs move as one 16-byte access
+#ifndef FFTEVP_ROW_PACK32
+#define FFTEVP_ROW_PACK32 2
+#endif
+template <typename T>
+constexpr int row_pack = sizeof(T) == 4 ? FFTEVP_ROW_PACK32 : 1;
+
+// rows -> LDS, all stages of the plan but the last (ends with a barrier)
+template <typename T, int N, int W, bool INV, int LS, bool FUSE>
+__device__ __forceinline__ void fft_head(const cx<T>* __restrict__ src, size_t rs, cx<T>* sh,
+                                         const cx<T>* __restrict__ tw) {
+  constexpr int NSL = last_stage_ns(N);
+  if constexpr (FUSE && NSL > 1) {
+    first_stage_from_rows<T, N, W, INV, LS, 256, row_pack<T>>(src, rs, sh);
+    fft_stages<T, N, radix_at(N, 1), NSL, INV, W, LS, 256>(sh, tw);
+  } else {
+    static_assert(LS == N + 1, "row copies use line stride N + 1");
+    rows_to_lines<T, N, W>(src, rs, sh);
+    __syncthreads();
+    fft_stages<T, N, 1, NSL, INV, W, LS, 256>(sh, tw);
+  }
+}
+// the plan's last stage, LDS -> rows
+template <typename T, int N, int W, bool INV, int LS, bool FUSE>
+__device__ __forceinline__ void fft_tail(const cx<T>* sh, const cx<T>* __restrict__ tw,
+                                         cx<T>* __restrict__ dst, size_t rs) {
+  if constexpr (FUSE) {
+    last_stage_to_rows<T, N, W, INV, LS, 256, row_pack<T>>(sh, tw, dst, rs);
+  } else {
+    constexpr int NSL = last_stage_ns(N);
+    fft_stages<T, N, NSL, N, INV, W, LS, 256>(const_cast<cx<T>*>(sh), tw);
+    lines_to_rows<T, N, W>(sh, dst, rs);
+  }
+}
+
 // FFT along y of TX x-frequencies x 6 components. The forward pass has one
 // extra row of blocks (blockIdx.y == 0): block b of that row reduces a
 // contiguous share of the local kernel's per-block partial sums, in a fixed
@@ -653,10 +702,9 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_ypass(YArgs<T> a) {
   const size_t rs = (size_t)a.h * 6;  // y stride
   const size_t z = red_row ? by - 1 : by;
   const size_t base = z * N1 * rs + (size_t)bx * W;
-  rows_to_lines<T, N1, W>(a.src + base, rs, sh);
-  __syncthreads();
-  fft_lines<T, N1, INV, W, N1 + 1, 256>(sh, a.tw);
-  lines_to_rows<T, N1, W>(sh, a.dst + base, rs);
+  constexpr bool FUSE = FFTEVP_FUSED_EDGE && N1 <= FFTEVP_FUSED_Y_MAX;
+  fft_head<T, N1, W, INV, N1 + 1, FUSE>(a.src + base, rs, sh, a.tw);
+  fft_tail<T, N1, W, INV, N1 + 1, FUSE>(sh, a.tw, a.dst + base, rs);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,9 +767,8 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zgamma(ZArgs<T> a) {
   const int ky = by, kx0 = bx * TX;
   const size_t zs = (size_t)n1 * H * 6;  // z stride
   cx<T>* __restrict__ buf = a.buf + ((size_t)ky * H + kx0) * 6;
-  rows_to_lines<T, N2, W>(buf, zs, sh);
-  __syncthreads();
-  fft_lines<T, N2, false, W, LS, 256>(sh, a.tw);
+  fft_head<T, N2, W, false, LS, FFTEVP_FUSED_EDGE>(buf, zs, sh, a.tw);
+  fft_stages<T, N2, last_stage_ns(N2), N2, false, W, LS, 256>(sh, a.tw);
 
   const T inv_n = T(a.inv_ntot);
   const T c_mu = T(1.0 / a.c0m), c_ratio = T((a.c0l + a.c0m) / (a.c0l + 2.0 * a.c0m));
@@ -763,8 +810,8 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zgamma(ZArgs<T> a) {
     for (int c = 0; c < 6; ++c) sh[(kx * 6 + c) * LS + z] = t[c];
   }
   __syncthreads();
-  fft_lines<T, N2, true, W, LS, 256>(sh, a.tw);
-  lines_to_rows<T, N2, W>(sh, buf, zs);
+  fft_stages<T, N2, 1, last_stage_ns(N2), true, W, LS, 256>(sh, a.tw);
+  fft_tail<T, N2, W, true, LS, FFTEVP_FUSED_EDGE>(sh, a.tw, buf, zs);
 }
 
 // ---------------------------------------------------------------------------
@@ -786,9 +833,8 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zspin(ZArgs<T> a) {
   const int ky = by, kx0 = bx * TX;
   const size_t zs = (size_t)n1 * H * 6;
   cx<T>* __restrict__ buf = a.buf + ((size_t)ky * H + kx0) * 6;
-  rows_to_lines<T, N2, W>(buf, zs, sh);
-  __syncthreads();
-  fft_lines<T, N2, false, W, LS, 256>(sh, a.tw);
+  fft_head<T, N2, W, false, LS, FFTEVP_FUSED_EDGE>(buf, zs, sh, a.tw);
+  fft_stages<T, N2, last_stage_ns(N2), N2, false, W, LS, 256>(sh, a.tw);
   const T scale = T(a.inv_ntot), h = T(kIR2);
   const int ky_s = ky < n1 / 2 ? ky : ky - n1;
   const bool nyq_y = (2 * ky == n1);
@@ -818,8 +864,8 @@ __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_zspin(ZArgs<T> a) {
     for (int c = 3; c < 6; ++c) sh[(kx * 6 + c) * LS + z] = {T(0), T(0)};
   }
   __syncthreads();
-  fft_lines<T, N2, true, W, LS, 256>(sh, a.tw);
-  lines_to_rows<T, N2, W>(sh, buf, zs);
+  fft_stages<T, N2, 1, last_stage_ns(N2), true, W, LS, 256>(sh, a.tw);
+  fft_tail<T, N2, W, true, LS, FFTEVP_FUSED_EDGE>(sh, a.tw, buf, zs);
 }
 
 template <typename T>
