@@ -1035,6 +1035,33 @@ constexpr IntVec12 kTv = cross_nd();
 constexpr int GND_GROUP = FFTEVP_GND_GROUP;
 static_assert(12 % GND_GROUP == 0, "GND system groups must divide 12");
 
+// Density rates of system al from the sample-frame gradient D of its slip
+// rate: (R v) . D = v . (R^T D) for the integer crystal-frame vectors d
+// (|d| = sqrt2) and t = n x d (|t| = sqrt6).
+template <typename T>
+__device__ __forceinline__ void gnd_system(int al, const double (&D)[3], const double (&R)[9], double cs_t,
+                                           double cs_d, T rv, T ev, T* rs_out, T* ret_out) {
+  double u[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) u[j] = R[j] * D[0] + R[3 + j] * D[1] + R[6 + j] * D[2];
+  double gd_ = 0.0, gt = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (kD[al][j] > 0) gd_ += u[j];
+    else if (kD[al][j] < 0) gd_ -= u[j];
+    if (kT[al][j] != 0) gt += kT[al][j] * u[j];
+  }
+  *rs_out = (T)((double)rv - cs_t * gt);
+  *ret_out = (T)((double)ev + cs_d * gd_);
+}
+
+// stencil weights along one axis: D = wp f(+) + wc f(0) + wm f(-)
+__device__ __forceinline__ void gnd_weights(bool p, bool m, double& wp, double& wc, double& wm) {
+  wp = p ? (m ? 0.5 : 1.0) : 0.0;
+  wm = m ? (p ? -0.5 : -1.0) : 0.0;
+  wc = (p && !m) ? -1.0 : ((m && !p) ? 1.0 : 0.0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
   const int nb = gridDim.x;
@@ -1057,12 +1084,7 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
   const int me = a.grain[g];
   double wp[3], wc[3], wm[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const bool p = a.grain[gp[k]] == me, m = a.grain[gm[k]] == me;
-    wp[k] = p ? (m ? 0.5 : 1.0) : 0.0;
-    wm[k] = m ? (p ? -0.5 : -1.0) : 0.0;
-    wc[k] = (p && !m) ? -1.0 : ((m && !p) ? 1.0 : 0.0);
-  }
+  for (int k = 0; k < 3; ++k) gnd_weights(a.grain[gp[k]] == me, a.grain[gm[k]] == me, wp[k], wc[k], wm[k]);
   double R[9];
   quat_rot<double>(a.quat[g], a.quat[a.V + g], a.quat[2 * a.V + g], a.quat[3 * a.V + g], R);
   const double cs = a.dt * a.inv_b * a.inv_h;
@@ -1091,21 +1113,97 @@ __global__ __launch_bounds__(256) void k_gnd(GndArgs<T> a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k)
         D[k] = wp[k] * (double)fv[q][1 + k] + wc[k] * (double)fv[q][0] + wm[k] * (double)fv[q][4 + k];
-      // (R v) . D = v . (R^T D) for the integer crystal-frame vectors
-      // d (|d| = sqrt2) and t = n x d (|t| = sqrt6)
-      double u[3];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) u[j] = R[j] * D[0] + R[3 + j] * D[1] + R[6 + j] * D[2];
-      double gd_ = 0.0, gt = 0.0;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        if (kD[al][j] > 0) gd_ += u[j];
-        else if (kD[al][j] < 0) gd_ -= u[j];
-        if (kT[al][j] != 0) gt += kT[al][j] * u[j];
-      }
-      rsv[(size_t)al * a.V + g] = (T)((double)rv[q] - cs_t * gt);
-      retv[(size_t)al * a.V + g] = (T)((double)ev[q] + cs_d * gd_);
+      gnd_system<T>(al, D, R, cs_t, cs_d, rv[q], ev[q], rsv + (size_t)al * a.V + g, retv + (size_t)al * a.V + g);
     }
+  }
+}
+
+// The same update marching along z: block (tile, chunk) takes 256
+// consecutive voxels of an xy-plane and walks ZC planes. The slip rates of
+// planes z-1, z and z+1 at its voxels stay in registers, so each plane of
+// slip rates is fetched once per chunk (plus two planes of halo) instead of
+// three times; the x and y neighbours are read while the neighbouring
+// threads, and the blocks of the neighbouring tiles running on the same XCD,
+// read them as their own. Needs n0 n1 a multiple of 256 and n2 of ZC.
+#ifndef FFTEVP_GND_MARCH
+#define FFTEVP_GND_MARCH 1
+#endif
+#ifndef FFTEVP_GND_WAVES
+#define FFTEVP_GND_WAVES 1
+#endif
+template <typename T, int ZC>
+__global__ __launch_bounds__(256, FFTEVP_GND_WAVES) void k_gnd_z(GndArgs<T> a) {
+  const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+  const size_t P = (size_t)n0 * n1, V = a.V;
+  const int ntile = (int)(P / 256), nb = gridDim.x;
+  int b = blockIdx.x;
+  if (FFTEVP_XCD_REMAP && nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
+  const int tile = b % ntile, z0 = (b / ntile) * ZC;
+  const size_t p = (size_t)tile * 256 + threadIdx.x;
+  const int x = (int)(p % n0), y = (int)(p / n0);
+  const size_t pxp = x + 1 < n0 ? p + 1 : p + 1 - n0, pxm = x > 0 ? p - 1 : p - 1 + n0;
+  const size_t pyp = y + 1 < n1 ? p + n0 : p + n0 - P, pym = y > 0 ? p - n0 : p - n0 + P;
+  const T* __restrict__ gdv = a.gd;
+  T* __restrict__ rsv = a.rs;
+  T* __restrict__ retv = a.ret;
+  const size_t zm = (size_t)(z0 > 0 ? z0 - 1 : n2 - 1) * P, zc0 = (size_t)z0 * P;
+  T f[12][3];  // slip rates of this column at z-1, z, z+1
+  int gz[3];   // grain ids at z-1, z, z+1
+#pragma unroll
+  for (int al = 0; al < 12; ++al) {
+    f[al][0] = gdv[(size_t)al * V + zm + p];
+    f[al][1] = gdv[(size_t)al * V + zc0 + p];
+  }
+  gz[0] = a.grain[zm + p];
+  gz[1] = a.grain[zc0 + p];
+  const double cs = a.dt * a.inv_b * a.inv_h;
+  const double cs_d = cs * kIR2, cs_t = cs * 0.40824829046386301637;  // 1/sqrt2, 1/sqrt6
+#pragma unroll
+  for (int st = 0; st < ZC; ++st) {
+    const int z = z0 + st;
+    const size_t bz = (size_t)z * P, bp = (size_t)(z + 1 < n2 ? z + 1 : 0) * P;
+    const size_t g = bz + p;
+#pragma unroll
+    for (int al = 0; al < 12; ++al) f[al][2] = gdv[(size_t)al * V + bp + p];
+    gz[2] = a.grain[bp + p];
+    const int me = gz[1];
+    double wp[3], wc[3], wm[3];
+    gnd_weights(a.grain[bz + pxp] == me, a.grain[bz + pxm] == me, wp[0], wc[0], wm[0]);
+    gnd_weights(a.grain[bz + pyp] == me, a.grain[bz + pym] == me, wp[1], wc[1], wm[1]);
+    gnd_weights(gz[2] == me, gz[0] == me, wp[2], wc[2], wm[2]);
+    double R[9];
+    quat_rot<double>(a.quat[g], a.quat[V + g], a.quat[2 * V + g], a.quat[3 * V + g], R);
+#pragma unroll
+    for (int grp = 0; grp < 12 / GND_GROUP; ++grp) {
+      T nv[GND_GROUP][4], rv[GND_GROUP], ev[GND_GROUP];  // x+, y+, x-, y- neighbours
+#pragma unroll
+      for (int q = 0; q < GND_GROUP; ++q) {
+        const T* __restrict__ fa = gdv + (size_t)(GND_GROUP * grp + q) * V + bz;
+        nv[q][0] = fa[pxp];
+        nv[q][1] = fa[pyp];
+        nv[q][2] = fa[pxm];
+        nv[q][3] = fa[pym];
+        rv[q] = rsv[(size_t)(GND_GROUP * grp + q) * V + g];
+        ev[q] = retv[(size_t)(GND_GROUP * grp + q) * V + g];
+      }
+#pragma unroll
+      for (int q = 0; q < GND_GROUP; ++q) {
+        const int al = GND_GROUP * grp + q;
+        const double c = (double)f[al][1];
+        double D[3];
+        D[0] = wp[0] * (double)nv[q][0] + wc[0] * c + wm[0] * (double)nv[q][2];
+        D[1] = wp[1] * (double)nv[q][1] + wc[1] * c + wm[1] * (double)nv[q][3];
+        D[2] = wp[2] * (double)f[al][2] + wc[2] * c + wm[2] * (double)f[al][0];
+        gnd_system<T>(al, D, R, cs_t, cs_d, rv[q], ev[q], rsv + (size_t)al * V + g, retv + (size_t)al * V + g);
+      }
+    }
+#pragma unroll
+    for (int al = 0; al < 12; ++al) {
+      f[al][0] = f[al][1];
+      f[al][1] = f[al][2];
+    }
+    gz[0] = gz[1];
+    gz[1] = gz[2];
   }
 }
 
@@ -1871,8 +1969,32 @@ hipError_t launch_export_int(const int* src, double* dst, size_t V, hipStream_t 
 }
 
 // GND update of one increment from the slip rates k_state left in gd.
+// Grids whose xy-planes hold whole blocks march along z in the longest
+// chunks (16, 8 or 4 planes) that still give a minimum number of blocks;
+// others take one thread per voxel. Longer chunks fetch fewer halo planes
+// (2 per chunk); FP32 (three waves per SIMD against two for FP64) measured
+// best with more, shorter chunks at 128^3: 512 and 2048 blocks minimum.
+#ifndef FFTEVP_GND_MIN_BLOCKS_F64
+#define FFTEVP_GND_MIN_BLOCKS_F64 512
+#endif
+#ifndef FFTEVP_GND_MIN_BLOCKS_F32
+#define FFTEVP_GND_MIN_BLOCKS_F32 2048
+#endif
 template <typename T>
 hipError_t launch_gnd(const GndArgs<T>& a, hipStream_t s) {
+  const size_t P = (size_t)a.n0 * a.n1;
+  if (FFTEVP_GND_MARCH && P % 256 == 0 && a.n2 % 4 == 0) {
+    const size_t tiles = P / 256;
+    const size_t min_blocks = sizeof(T) == 8 ? FFTEVP_GND_MIN_BLOCKS_F64 : FFTEVP_GND_MIN_BLOCKS_F32;
+    auto fits = [&](int zc) { return a.n2 % zc == 0 && tiles * (a.n2 / zc) >= min_blocks; };
+    if (fits(16))
+      hipLaunchKernelGGL((k_gnd_z<T, 16>), dim3((unsigned)(tiles * (a.n2 / 16))), dim3(256), 0, s, a);
+    else if (fits(8))
+      hipLaunchKernelGGL((k_gnd_z<T, 8>), dim3((unsigned)(tiles * (a.n2 / 8))), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_gnd_z<T, 4>), dim3((unsigned)(tiles * (a.n2 / 4))), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   const int nb = (int)((a.V + 255) / 256);
   hipLaunchKernelGGL(k_gnd<T>, dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -94,3 +94,44 @@ def test_gnd_snapshots_and_errors(require_gpu):
     with pytest.raises(FftevpError) as e:
         t.set_gnd(np.zeros(4096, np.int32), -1.0, 200.0)
     assert e.value.status == EINVAL
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_gnd_full_grid(require_gpu, precision, bound):
+    """128^3, 500 grains: the GND kernel at the benchmark size (z-marching in
+    chunks of 16 planes in FP64, 4 in FP32) against the oracle's GND update
+    of the first increment, evaluated on the GPU's converged stress,
+    orientations and starting densities: the oracle's slip rates (flow rule
+    at the increment-start density), then its grain-aware gradients. The
+    densities start at zero, so they are dt times the rates. Bound relative
+    to the field maximum; mixed stores FP32 stresses, rates and densities."""
+    from paper_1509_04953_amd import Solver, Material, Load, Opts
+    from oracle import Flow, CU
+    from oracle import local as Lc
+    from oracle.crystal import voxel_material
+    from oracle.gnd import gnd_rates
+    from oracle.tensors import voigt_to_mandel
+    w = synth.workload("cu128")
+    quat, rho, grains = synth.make_microstructure(w)
+    s = Solver(w.shape, precision)
+    s.set_material(Material())
+    s.set_microstructure(quat.reshape(4, -1), rho.reshape(-1))
+    s.set_loading(Load(dt=w.dt))
+    s.set_gnd(grains.reshape(-1), L0, XI)
+    rho0 = s.field("rho").cpu().numpy()
+    print(f"case: GND 128^3 {precision} increment 1", flush=True)
+    r = s.step(Opts(tol=w.tol, max_iter=2000))
+    assert r.status == 0
+    sig = s.field("sigma").cpu().numpy()
+    q = s.field("quat").cpu().numpy()
+    got = [s.field(k).cpu().numpy() for k in ("rho_gnds", "rho_gndet")]
+    s.close()
+    f = Flow()
+    _, _, m = voxel_material(q, **CU)
+    tauc = f.tau0 + f.alpha * f.mu * f.b * np.sqrt(rho0)
+    _, gd = Lc.slip_rates(voigt_to_mandel(sig).T, m, tauc, f.gdot0, f.n)
+    want = [w.dt * x for x in gnd_rates(gd.T, q, grains.reshape(-1), w.shape, f.b, L0)]
+    for k, g, v in zip(("rho_gnds", "rho_gndet"), got, want):
+        assert np.abs(v).max() > 0
+        print(k, precision, rel(g, v), flush=True)
+        assert rel(g, v) < bound, (k, rel(g, v))
