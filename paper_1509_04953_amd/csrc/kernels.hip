@@ -630,12 +630,14 @@ __device__ __forceinline__ void lines_to_rows(const cx<T>* sh, cx<T>* __restrict
 #ifndef FFTEVP_FUSED_Y_MAX
 #define FFTEVP_FUSED_Y_MAX 128
 #endif
-// lines per thread at the edges: FP32 pairs move as one 16-byte access
-#ifndef FFTEVP_ROW_PACK32
-#define FFTEVP_ROW_PACK32 2
+// lines per thread at the edges: FP32 lines of 256+ points move in pairs as
+// one 16-byte access (z pass 8 % faster at 256^3), shorter ones singly (z
+// pass 8 % faster at 128^3, where a tile has twice the lines)
+#ifndef FFTEVP_ROW_PACK32_MIN_N
+#define FFTEVP_ROW_PACK32_MIN_N 256
 #endif
-template <typename T>
-constexpr int row_pack = sizeof(T) == 4 ? FFTEVP_ROW_PACK32 : 1;
+template <typename T, int N>
+constexpr int row_pack = (sizeof(T) == 4 && N >= FFTEVP_ROW_PACK32_MIN_N) ? 2 : 1;
 
 // rows -> LDS, all stages of the plan but the last (ends with a barrier)
 template <typename T, int N, int W, bool INV, int LS, bool FUSE>
@@ -643,7 +645,7 @@ __device__ __forceinline__ void fft_head(const cx<T>* __restrict__ src, size_t r
                                          const cx<T>* __restrict__ tw) {
   constexpr int NSL = last_stage_ns(N);
   if constexpr (FUSE && NSL > 1) {
-    first_stage_from_rows<T, N, W, INV, LS, 256, row_pack<T>>(src, rs, sh);
+    first_stage_from_rows<T, N, W, INV, LS, 256, row_pack<T, N>>(src, rs, sh);
     fft_stages<T, N, radix_at(N, 1), NSL, INV, W, LS, 256>(sh, tw);
   } else {
     static_assert(LS == N + 1, "row copies use line stride N + 1");
@@ -657,7 +659,7 @@ template <typename T, int N, int W, bool INV, int LS, bool FUSE>
 __device__ __forceinline__ void fft_tail(const cx<T>* sh, const cx<T>* __restrict__ tw,
                                          cx<T>* __restrict__ dst, size_t rs) {
   if constexpr (FUSE) {
-    last_stage_to_rows<T, N, W, INV, LS, 256, row_pack<T>>(sh, tw, dst, rs);
+    last_stage_to_rows<T, N, W, INV, LS, 256, row_pack<T, N>>(sh, tw, dst, rs);
   } else {
     constexpr int NSL = last_stage_ns(N);
     fft_stages<T, N, NSL, N, INV, W, LS, 256>(const_cast<cx<T>*>(sh), tw);
@@ -673,6 +675,7 @@ __device__ __forceinline__ void fft_tail(const cx<T>* sh, const cx<T>* __restric
 #ifndef FFTEVP_SPEC_WAVES
 #define FFTEVP_SPEC_WAVES 1
 #endif
+
 
 template <typename T, int N1, int TX, bool INV>
 __global__ __launch_bounds__(256, FFTEVP_SPEC_WAVES) void k_ypass(YArgs<T> a) {
