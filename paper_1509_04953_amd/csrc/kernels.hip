@@ -487,25 +487,37 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
 // holds one x-frequency, whose 96-byte row segments straddle cache lines
 // that neighbouring tiles complete (measured at 256^3: the y passes wrote
 // 1.3x their bytes); two x-frequencies (49 KB, three blocks per CU) ran the
-// FP64 y and z passes 23-27 % faster there. FP32 tiles and shorter lines
-// measured fastest at 25 KB.
+// FP64 y and z passes 23-27 % faster there. Shorter lines measured fastest
+// at 25 KB.
 #ifndef FFTEVP_SPEC_LDS_KB_F64_LONG
 #define FFTEVP_SPEC_LDS_KB_F64_LONG 50
 #endif
+// FP32 lines of 256+ points: the z pass and the inverse y pass take 50 KB
+// tiles too (four x-frequencies, rows of 192 B instead of 96 B that two
+// tiles share a cache line of): 20 % and 11 % faster at 256^3; the forward
+// y pass, which also reduces the local kernel's partials, measured 7 %
+// slower with them and keeps 25 KB.
+#ifndef FFTEVP_SPEC_LDS_KB_F32_LONG
+#define FFTEVP_SPEC_LDS_KB_F32_LONG 50
+#endif
+#ifndef FFTEVP_Y_FWD_WIDE32
+#define FFTEVP_Y_FWD_WIDE32 0
+#endif
 template <typename T>
-__host__ __device__ constexpr int spec_budget_kb(int n, int kb) {
-  return (sizeof(T) == 8 && n >= 256) ? FFTEVP_SPEC_LDS_KB_F64_LONG : kb;
+__host__ __device__ constexpr int spec_budget_kb(int n, int kb, bool wide32) {
+  if (n < 256) return kb;
+  return sizeof(T) == 8 ? FFTEVP_SPEC_LDS_KB_F64_LONG : (wide32 ? FFTEVP_SPEC_LDS_KB_F32_LONG : kb);
 }
 template <typename T>
-__host__ __device__ constexpr int spec_tile(int n, int kb = FFTEVP_SPEC_LDS_KB) {
+__host__ __device__ constexpr int spec_tile(int n, int kb = FFTEVP_SPEC_LDS_KB, bool wide32 = true) {
   int tx = 16;
-  const int budget = spec_budget_kb<T>(n, kb);
+  const int budget = spec_budget_kb<T>(n, kb, wide32);
   while (tx > 1 && 6 * tx * (n + 1) * 2 * (int)sizeof(T) > budget * 1024) tx /= 2;
   return tx;
 }
-template <typename T>
+template <typename T, bool INV>
 __host__ __device__ constexpr int y_tile(int n) {
-  return spec_tile<T>(n, FFTEVP_Y_LDS_KB);
+  return spec_tile<T>(n, FFTEVP_Y_LDS_KB, INV || FFTEVP_Y_FWD_WIDE32);
 }
 
 // Workgroups are dealt round-robin to the eight XCDs, each with its own L2.
@@ -1801,7 +1813,7 @@ int local_blocks(int n0, int n1, int n2) {
 // number of x-frequency tiles of a y pass (= blocks in its reduction row)
 template <typename T>
 int ypass_tiles(int n1, int h) {
-  const int tx = y_tile<T>(n1);
+  const int tx = y_tile<T, false>(n1);
   return h / (h < tx ? h : tx);
 }
 
@@ -1819,13 +1831,13 @@ hipError_t ypass_tx(int n2, const YArgs<T>& a, hipStream_t s) {
 template <typename T, bool INV>
 hipError_t launch_ypass(int n1, int n2, const YArgs<T>& a, hipStream_t s) {
   switch (n1) {
-    case 8: return ypass_tx<T, 8, y_tile<T>(8), INV>(n2, a, s);
-    case 16: return ypass_tx<T, 16, y_tile<T>(16), INV>(n2, a, s);
-    case 32: return ypass_tx<T, 32, y_tile<T>(32), INV>(n2, a, s);
-    case 64: return ypass_tx<T, 64, y_tile<T>(64), INV>(n2, a, s);
-    case 128: return ypass_tx<T, 128, y_tile<T>(128), INV>(n2, a, s);
-    case 256: return ypass_tx<T, 256, y_tile<T>(256), INV>(n2, a, s);
-    case 512: return ypass_tx<T, 512, y_tile<T>(512), INV>(n2, a, s);
+    case 8: return ypass_tx<T, 8, y_tile<T, INV>(8), INV>(n2, a, s);
+    case 16: return ypass_tx<T, 16, y_tile<T, INV>(16), INV>(n2, a, s);
+    case 32: return ypass_tx<T, 32, y_tile<T, INV>(32), INV>(n2, a, s);
+    case 64: return ypass_tx<T, 64, y_tile<T, INV>(64), INV>(n2, a, s);
+    case 128: return ypass_tx<T, 128, y_tile<T, INV>(128), INV>(n2, a, s);
+    case 256: return ypass_tx<T, 256, y_tile<T, INV>(256), INV>(n2, a, s);
+    case 512: return ypass_tx<T, 512, y_tile<T, INV>(512), INV>(n2, a, s);
     default: return hipErrorInvalidValue;
   }
 }
