@@ -169,6 +169,37 @@ def test_curve_64cube_matches_golden(require_gpu):
     assert np.abs(rho - np.array(d["rho_sample"])).max() < 1e-10 * np.max(d["rho_sample"])
 
 
+def test_curve_128cube_first_increment_matches_golden(require_gpu):
+    """128^3, 500 grains, log-normal density (the benchmark configuration),
+    FP64 at its stop tolerance 1e-6: the oracle's first increment, 87
+    fixed-point iterations (stored by tests/golden/make_golden.py): the same
+    iteration count, the mean stress and the macroscopic strain within
+    1e-10, and the stress, strain, plastic strain and density at 256 sampled
+    voxels within 1e-10 of the sample's largest magnitude."""
+    from paper_1509_04953_amd import Opts
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "curve_128cube.json")))
+    w = synth.workload("cu128")
+    assert d["workload"] == "cu128" and d["tol"] == w.tol
+    s, _, _ = make(w, "fp64")
+    print("case: 128^3 fp64 first increment against the oracle", flush=True)
+    r = s.step(Opts(tol=w.tol, max_iter=2000))
+    assert r.status == 0
+    assert r.iters == d["iters"][0], (r.iters, d["iters"][0])
+    S = np.array(d["Sigma"][0])
+    assert np.abs(np.array(r.Sigma) - S).max() < 1e-10 * np.abs(S).max()
+    assert np.allclose(r.E, d["E"][0], rtol=1e-10, atol=1e-15)
+    idx = np.array(d["sample_index"])
+    for k, key in (("sigma", "sigma_sample"), ("strain", "strain_sample"), ("epsp", "epsp_sample"),
+                   ("rho", "rho_sample")):
+        g = s.field(k).cpu().numpy()
+        g = g[:, idx] if g.ndim == 2 else g[idx]
+        v = np.array(d[key])
+        err = np.abs(g - v).max() / np.abs(v).max()
+        print(k, "max relative difference", err, flush=True)
+        assert err < 1e-10, (k, err)
+    s.close()
+
+
 def test_mixed_vs_fp64_128(require_gpu):
     """128^3, 500 grains, the whole path of the mixed-precision configuration
     (100 increments to 20 % strain): per-field relative L2 errors of the
