@@ -496,22 +496,25 @@ __device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d
 __device__ __forceinline__ double recip(double d) { return 1.0 / d; }
 
 // Solve J x = rhs for SPD J (packed lower triangle) by J = L D L^T with unit
-// lower L. P holds L scaled by D column-wise (P_ij = L_ij d_j), id = 1/d.
+// lower L. P holds L scaled by D column-wise (P_ij = L_ij d_j), id = 1/d;
+// L_ij = P_ij id_j is formed once per entry, so every update of the
+// factorisation and of the forward substitution is one fused multiply-add.
 template <typename T>
 __device__ __forceinline__ void ldl_solve(const T (&J)[21], const T (&rhs)[6], T (&x)[6]) {
-  T P[21], id[6];
+  T P[21], L[21], id[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     T d = J[tri(j, j)];
 #pragma unroll
-    for (int k = 0; k < j; ++k) d -= P[tri(j, k)] * P[tri(j, k)] * id[k];
+    for (int k = 0; k < j; ++k) d -= P[tri(j, k)] * L[tri(j, k)];
     id[j] = recip(d);
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       T v = J[tri(i, j)];
 #pragma unroll
-      for (int k = 0; k < j; ++k) v -= P[tri(i, k)] * P[tri(j, k)] * id[k];
+      for (int k = 0; k < j; ++k) v -= P[tri(i, k)] * L[tri(j, k)];
       P[tri(i, j)] = v;
+      L[tri(i, j)] = v * id[j];
     }
   }
   T y[6];  // L y = rhs
@@ -519,15 +522,15 @@ __device__ __forceinline__ void ldl_solve(const T (&J)[21], const T (&rhs)[6], T
   for (int i = 0; i < 6; ++i) {
     T v = rhs[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) v -= P[tri(i, k)] * id[k] * y[k];
+    for (int k = 0; k < i; ++k) v -= L[tri(i, k)] * y[k];
     y[i] = v;
   }
 #pragma unroll
   for (int i = 5; i >= 0; --i) {  // L^T x = D^-1 y
-    T v = y[i];
+    T v = y[i] * id[i];
 #pragma unroll
-    for (int k = i + 1; k < 6; ++k) v -= P[tri(k, i)] * x[k];
-    x[i] = v * id[i];
+    for (int k = i + 1; k < 6; ++k) v -= L[tri(k, i)] * x[k];
+    x[i] = v;
   }
 }
 
