@@ -311,12 +311,19 @@ fftevp_status fftevp_load_state(fftevp_ctx* ctx, const void* src_dev);
  * strain-controlled components matter, the others are fixed by the loading).
  * adj_state_dev (device, caller-owned, fftevp_adjoint_bytes() bytes, zero it
  * before the last increment): adjoint of the state after the increment on
- * entry, adjoint of the state before it on return. dL_dtheta[4] (host,
+ * entry, adjoint of the state before it on return. It also keeps the
+ * converged solution of the implicit linear problem, from which the next
+ * call (the increment before) starts its iteration: pass the same workspace
+ * through the whole reverse walk, whatever the checkpoint schedule (each
+ * call then starts from its successor's solution, so schedules give
+ * bit-identical gradients). dL_dtheta[4] (host,
  * d/d(tau0, k1, k2, n)) is accumulated. The implicit linear problem is
  * solved with the same spectral iteration, to opts->tol; in MIXED precision
  * to max(opts->tol, 1e-5), since FP32 fields stall the tangent residual
  * near that level once the adjoint state has accumulated over many
- * increments (the gradient is then within ~1e-5 of the FP64 one). The call
+ * increments (the gradient is then within ~1e-5 of the FP64 one). Its
+ * boundary residual (stress-controlled mean components) is measured against
+ * the stress scale 2 mu0 |strain| of the problem's right-hand side. The call
  * allocates nothing: it reuses the context's state buffers, so load a
  * snapshot before the next fftevp_step (ESTATE otherwise). */
 size_t fftevp_adjoint_bytes(const fftevp_ctx* ctx);

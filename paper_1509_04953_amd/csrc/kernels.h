@@ -44,6 +44,7 @@ struct FinArgs {
   int nblocks;
   double nvox, tol;
   double enorm;        // > 0: normalises err_c instead of |E|
+  double sscale;       // > 0: normalises err_bc instead of |Sigma| (the adjoint's stress scale)
   int strain_ctrl[6];
   double sig_star[6];  // Mandel
   double css[36];      // [(C0)_ss]^-1 embedded in 6x6 (Mandel), zero elsewhere

@@ -905,7 +905,8 @@ __device__ void finalize_sums(const FinArgs& a, Ctl* ctl, const double (&tot)[NP
     nbc += dS[k] * dS[k];
   }
   const double err_c = sqrt(tot[0] * iv) / (a.enorm > 0.0 ? a.enorm : sqrt(nE));
-  const double err_bc = nS > 0.0 ? sqrt(nbc / nS) : (nbc == 0.0 ? 0.0 : INFINITY);
+  const double err_bc = a.sscale > 0.0 ? sqrt(nbc) / a.sscale
+                                       : (nS > 0.0 ? sqrt(nbc / nS) : (nbc == 0.0 ? 0.0 : INFINITY));
   for (int k = 0; k < 6; ++k) ctl->Sigma[k] = Sig[k];
   ctl->err_c = err_c;
   ctl->err_bc = err_bc;
