@@ -11,9 +11,10 @@ end-of-increment state update. W untimed increments come first, then K timed
 ones. The FP64 path gives ``value``; the mixed-precision path (FP32 fields,
 transforms and Newton; FP64 reductions and macroscopic update) is timed the
 same way and reported under ``mixed``. ``adjoint`` reports the wall time of
-the curve-loss gradient (backward, with segment recomputation from sqrt(T)
-checkpoints) over that of the forward pass, on the 128^3 / 300-grain /
-40-increment workload.
+the curve-loss gradient (backward, with segment recomputation from the
+checkpoints of the memory-aware schedule: every increment's state when all
+fit in half of the free device memory) over that of the forward pass, on the
+128^3 / 300-grain / 40-increment workload.
 
 voxel-iterations/s = sum over timed increments of (fixed-point iterations x
 voxels) / wall time, with inputs resident in HBM. Per-kernel durations come
@@ -119,7 +120,7 @@ def run_adjoint(w, quat, rho, precision, increments=None):
     return {"workload": f"{w.shape[0]}^3, {w.n_grains} grains, {T} increments",
             "precision": precision, "forward_s": t1 - t0, "backward_s": t2 - t1,
             "adjoint_over_forward": (t2 - t1) / (t1 - t0),
-            "checkpoint_every": int(np.ceil(np.sqrt(T))),
+            "checkpoint_every": int(p.schedule),
             "forward_iterations": its,
             "forward_voxel_iterations_per_s": its * w.voxels / (t1 - t0),
             "final_strain": -w.d_eps * T, "s33_final": float(c.detach()[-1]),

@@ -7,10 +7,14 @@ the library's adjoint of each converged increment (implicit differentiation
 of the fixed point, one linear tangent solve per increment).
 
 Memory: the forward keeps a state snapshot every ``checkpoint_every``
-increments (default ~sqrt(T)); the backward recomputes one segment at a time
-from its checkpoint, keeping that segment's snapshots, then walks it in
-reverse. Recomputation is bit-identical because every kernel is
-deterministic.
+increments, and after the last one; the backward recomputes one segment at a
+time from its checkpoint (the segment's end is the next checkpoint, so k - 1
+increments per segment of k), keeping that segment's snapshots, then walks it
+in reverse. The default interval is the smallest whose snapshots fit in half
+of the free device memory: every increment's state when they all fit (no
+recomputation at all), else longer segments, at most ceil(sqrt T).
+Recomputation is bit-identical because every kernel is deterministic, so
+every schedule gives the same gradient.
 """
 from __future__ import annotations
 
@@ -33,8 +37,9 @@ class CurveProblem:
     increments: int
     opts: Opts = None
     adjoint_opts: Opts = None
-    checkpoint_every: int = 0
+    checkpoint_every: int = 0  # 0: the smallest interval that fits in memory (see the module notes)
     iterations: list = None   # fixed-point iterations of the latest forward, per increment
+    schedule: int = 0         # checkpoint interval of the latest forward
 
 
 def _material(base: Material, theta) -> Material:
@@ -56,9 +61,25 @@ def _forward(p: CurveProblem, theta, keep_every):
             raise RuntimeError(f"increment {t} did not converge (status {r.status})")
         curve.append(r.Sigma[2])
         p.iterations.append(r.iters)
-        if keep_every and t % keep_every == 0 and t < p.increments:
+        if keep_every and (t % keep_every == 0 or t == p.increments):
             ckpts[t] = s.save_state()
     return np.array(curve), ckpts
+
+
+def _schedule(p: CurveProblem) -> int:
+    """Checkpoint interval k: the smallest with ceil(T / k) + 1 checkpoints
+    plus the k - 1 recomputed states of one segment within half of the free
+    device memory; ceil(sqrt T) when even that does not fit."""
+    T = p.increments
+    if p.checkpoint_every:
+        return p.checkpoint_every
+    k_max = max(1, int(math.ceil(math.sqrt(T))))
+    snap = p.solver.state_bytes()
+    free, _ = torch.cuda.mem_get_info()
+    for k in range(1, k_max):
+        if (math.ceil(T / k) + 1 + (k - 1)) * snap <= 0.5 * free:
+            return k
+    return k_max
 
 
 def curve(p: CurveProblem, theta):
@@ -70,8 +91,8 @@ def curve(p: CurveProblem, theta):
 class StressStrainCurve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, p: CurveProblem):
-        T = p.increments
-        every = p.checkpoint_every or max(1, int(math.ceil(math.sqrt(T))))
+        every = _schedule(p)
+        p.schedule = every
         c, ckpts = _forward(p, theta.detach().cpu().numpy(), every)
         ctx.p, ctx.every, ctx.ckpts = p, every, ckpts
         ctx.theta = theta.detach().cpu().numpy()
@@ -93,11 +114,15 @@ class StressStrainCurve(torch.autograd.Function):
         adj = torch.zeros(s.adjoint_bytes(), dtype=torch.uint8, device="cuda")
         dth = np.zeros(4)
         starts = sorted(ckpts)
-        for a in reversed(starts):
+        for a in reversed(starts[:-1] if starts[-1] == T else starts):
             b = min(a + every, T)
-            s.load_state(ckpts[a])
             states = [ckpts[a]]
-            for _ in range(a + 1, b + 1):
+            if b - a > 1:
+                s.load_state(ckpts[a])
+            for t in range(a + 1, b + 1):
+                if t in ckpts:      # the segment's end: stored by the forward
+                    states.append(ckpts[t])
+                    continue
                 r = s.step(p.opts)
                 if r.status != OK:
                     raise RuntimeError("recomputation did not converge")

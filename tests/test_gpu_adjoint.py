@@ -106,8 +106,9 @@ def test_two_curves_in_one_loss(require_gpu):
 def test_adjoint_128_forty_increments(require_gpu):
     """The adjoint configuration: 128^3, 300 grains, 40 increments, loss
     against the curve of the perturbed parameters theta0 * (1.05, 0.95,
-    1.05, 0.95), default checkpoints (every ceil(sqrt 40) = 7): the adjoint
-    gradient against central differences of the GPU forward (FP64)."""
+    1.05, 0.95), default checkpoint schedule (memory-aware: at this size every
+    increment's state fits, so nothing is recomputed): the adjoint gradient
+    against central differences of the GPU forward (FP64)."""
     import torch
     from paper_1509_04953_amd import Solver, Material, Load, Opts
     from paper_1509_04953_amd.adjoint import CurveProblem, curve
