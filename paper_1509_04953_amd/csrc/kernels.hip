@@ -317,7 +317,18 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
         T phi1, cand[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * T(d[k]);
-        local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, sp);
+        if constexpr (FLOW == FLOW_MR && sizeof(T) == 8) {
+          // FP64: the per-system parameters are re-read (from cache) at every
+          // evaluation through a pointer made opaque per pass, instead of
+          // being hoisted out of the loop into 72 live registers (two waves
+          // per SIMD instead of one: 6 % faster; FP32 kept them, 12 % faster)
+          uint64_t pp = reinterpret_cast<uint64_t>(sp.p);
+          asm volatile("" : "+s"(pp));
+          const SysParams<T> spp{reinterpret_cast<const T*>(pp), sp.V, sp.g};
+          local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, spp);
+        } else {
+          local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, sp);
+        }
         float rn1 = 0.f;
 #pragma unroll
         for (int k = 0; k < 6; ++k) rn1 += r[k] * r[k];
