@@ -277,7 +277,7 @@ fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_repor
  * memory (tight serving loops, harnesses that forbid hipMalloc). Same
  * increment, same kernels and bit-identical results as fftevp_step; the
  * increment's scratch (per-block partial sums, first-stage sums, control
- * block, reduction pair: about 6.3 MB) lives in a static device array of
+ * block, reduction pair: about 12.6 MB) lives in a static device array of
  * the library instead of the context, one copy per device, held until the
  * process ends. The context must have been created (fftevp_create allocates
  * its fields as before); the call itself allocates nothing, device or

@@ -1393,15 +1393,15 @@ fftevp_status fftevp_step(fftevp_ctx* ctx, const fftevp_opts* opts, fftevp_repor
 // fftevp_step_noalloc: the scratch of an increment in a static device array
 // ---------------------------------------------------------------------------
 // The increment's scratch is small next to its fields: the local kernel's
-// per-block partial sums (NPART per block of 256 voxels, or of 512 when
-// n0 = 512), the first-stage sums of the forward y pass (NPART per
+// per-block partial sums (NPART per block of at least FFTEVP_LOCAL_VPB
+// voxels), the first-stage sums of the forward y pass (NPART per
 // x-frequency tile, at most 256 tiles), the
 // control block, and the end-of-increment reduction pair. For grids of at
 // most 2^24 voxels it fits the array below; each device that runs the entry
 // point holds its own copy until the process ends.
 namespace {
 constexpr size_t kNaMaxVoxels = size_t(1) << 24;
-constexpr size_t kNaPartial = kNaMaxVoxels / 256 * NPART;  // doubles (>= 1024 x 4)
+constexpr size_t kNaPartial = kNaMaxVoxels / FFTEVP_LOCAL_VPB * NPART;  // doubles (>= 1024 x 4)
 constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 constexpr size_t kNaOffStage1 = round256(kNaPartial * sizeof(double));
 constexpr int kNaMaxTiles = 256;  // x-frequency tiles of a y pass: n0 / 2 <= 256, at least one per tile

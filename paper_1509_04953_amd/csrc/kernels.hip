@@ -61,41 +61,44 @@ __device__ __forceinline__ void block_reduce(double (&v)[NP], double* __restrict
   }
 }
 
-// Block of 256 threads, reduction through LDS (scratch: NP * 288 doubles):
-// every thread stores its NP values; 16 threads per value combine 16 entries
-// each (thread c takes entries c, c + 16, ...); one thread per value combines
-// those 16 results. The last NMAX values are reduced by max. Fixed order.
-template <int NP, int NMAX>
+// Block of NT threads (128 or 256), reduction through LDS (scratch:
+// NP * (NT + 32) doubles): every thread stores its NP values; C threads per
+// value (16, or 8 when 16 NP exceeds NT) combine NT / C entries each (thread
+// c takes entries c, c + C, ...); one thread per value combines those C
+// results. The last NMAX values are reduced by max. Fixed order.
+template <int NP, int NMAX, int NT>
 __device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], double* red,
                                                  double* __restrict__ out, size_t stride) {
-  constexpr int RS = 272;  // row stride: rows of adjacent values fall on other banks
+  constexpr int C = NP * 16 <= NT ? 16 : 8;
+  static_assert(NT % C == 0 && NP * C <= NT, "one thread per (value, column)");
+  constexpr int RS = NT + 16;  // row stride: rows of adjacent values fall on other banks
   double* red2 = red + NP * RS;
   const int t = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < NP; ++k) red[k * RS + t] = v[k];
   __syncthreads();
-  if (t < NP * 16) {
-    const int k = t >> 4, c = t & 15;
+  if (t < NP * C) {
+    const int k = t / C, c = t % C;
     const double* row = red + k * RS + c;
     double r = row[0];
     if (k >= NP - NMAX) {
 #pragma unroll
-      for (int i = 1; i < 16; ++i) r = fmax(r, row[16 * i]);
+      for (int i = 1; i < NT / C; ++i) r = fmax(r, row[C * i]);
     } else {
 #pragma unroll
-      for (int i = 1; i < 16; ++i) r += row[16 * i];
+      for (int i = 1; i < NT / C; ++i) r += row[C * i];
     }
     red2[t] = r;
   }
   __syncthreads();
   if (t < NP) {
-    double r = red2[16 * t];
+    double r = red2[C * t];
     if (t >= NP - NMAX) {
 #pragma unroll
-      for (int i = 1; i < 16; ++i) r = fmax(r, red2[16 * t + i]);
+      for (int i = 1; i < C; ++i) r = fmax(r, red2[C * t + i]);
     } else {
 #pragma unroll
-      for (int i = 1; i < 16; ++i) r += red2[16 * t + i];
+      for (int i = 1; i < C; ++i) r += red2[C * t + i];
     }
     out[t * stride] = r;
   }
@@ -106,8 +109,8 @@ __device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], double* 
 // ---------------------------------------------------------------------------
 template <typename T, int N0>
 struct LocalShape {
-  static constexpr int NT = 256;
   static constexpr int LPB = local_lines_per_block(N0);  // x-lines per block
+  static constexpr int NT = LPB * N0 < 256 ? LPB * N0 : 256;
   static constexpr int VPT = LPB * N0 / NT;              // voxels per thread
   static constexpr int LS = N0 + 1;                    // LDS line stride
   static constexpr int H = N0 / 2;
@@ -182,14 +185,14 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
 // a positive integer, FLOW_MR for the paper's law; the host picks the
 // instance).
 template <typename T, int N0, int MODE, int FLOW>
-__global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_WAVES : FFTEVP_MR_WAVES_F32) : (sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32)) void k_local(
+__global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_WAVES : FFTEVP_MR_WAVES_F32) : (sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32)) void k_local(
     LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
   if (a.ctl && a.ctl->done) return;
   // LDS: the six strain/polarisation lines (complex pairs), later reused by
   // the block reduction
   constexpr int SH_BYTES = 3 * S::LPB * S::LS * (int)sizeof(cx<T>);
-  constexpr int RED_BYTES = NPART * 288 * (int)sizeof(double);
+  constexpr int RED_BYTES = NPART * (S::NT + 32) * (int)sizeof(double);
   __shared__ __align__(16) unsigned char lds[SH_BYTES > RED_BYTES ? SH_BYTES : RED_BYTES];
   cx<T>* sh = reinterpret_cast<cx<T>*>(lds);
   const size_t planes = (size_t)a.n1 * a.n2;
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(256, FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_
     for (int k = 0; k < 6; ++k) a.e_nyq_next[(line0 + l) * 6 + k] = s * en[k];
   }
   __syncthreads();  // the line buffer is reused below
-  block_reduce_lds<NPART, 1>(part, reinterpret_cast<double*>(lds), a.partial + blockIdx.x, gridDim.x);
+  block_reduce_lds<NPART, 1, S::NT>(part, reinterpret_cast<double*>(lds), a.partial + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1792,14 +1795,14 @@ hipError_t launch_local(int n0, const LocalArgs<T>& a, hipStream_t s) {
     const int lpb = LocalShape<T, N>::LPB;                                                    \
     if constexpr (MODE == MODE_NEWTON) {                                                      \
       if (a.sysp) {                                                                           \
-        hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_MR>), dim3(planes / lpb), dim3(256), 0, s, a); \
+        hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_MR>), dim3(planes / lpb), dim3(LocalShape<T, N>::NT), 0, s, a); \
         break;                                                                                \
       }                                                                                       \
     }                                                                                         \
     if (MODE == MODE_EXPORT || a.m.n_int > 0)                                                 \
-      hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_POWER_INT>), dim3(planes / lpb), dim3(256), 0, s, a); \
+      hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_POWER_INT>), dim3(planes / lpb), dim3(LocalShape<T, N>::NT), 0, s, a); \
     else                                                                                      \
-      hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_POWER>), dim3(planes / lpb), dim3(256), 0, s, a); \
+      hipLaunchKernelGGL((k_local<T, N, MODE, FLOW_POWER>), dim3(planes / lpb), dim3(LocalShape<T, N>::NT), 0, s, a); \
     break;                                                                                    \
   }
   switch (n0) {
