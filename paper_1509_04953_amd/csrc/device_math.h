@@ -75,6 +75,23 @@ struct SysParams {
   __device__ __forceinline__ T amp(int a) const { return p[(size_t)(24 + a) * V + g]; }
 };
 
+// The same parameters with the first Q rows (tau_pass and 1/tau_cut: 24, or
+// all 36) staged in LDS, one column per thread (rows of stride ls); the rest
+// read from global memory.
+template <typename T, int Q>
+struct SysParamsStaged {
+  const T* p;
+  size_t V, g;
+  const T* l;
+  int ls, t;
+  __device__ __forceinline__ T tp(int a) const { return l[a * ls + t]; }
+  __device__ __forceinline__ T itc(int a) const { return l[(12 + a) * ls + t]; }
+  __device__ __forceinline__ T amp(int a) const {
+    if constexpr (Q == 36) return l[(24 + a) * ls + t];
+    else return p[(size_t)(24 + a) * V + g];
+  }
+};
+
 // 1/x: the hardware reciprocal, refined once by Newton's method in FP64
 __device__ __forceinline__ float fast_recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_recip(double x) {
@@ -311,8 +328,8 @@ __device__ __forceinline__ void flow_type(const T (&s)[6], T cn, T cs, T n, int 
 // weight dgdot/dtau = A cosh(x) / tau_cut and potential A tau_cut (cosh x - 1)
 // (zero below the passing stress). g, visc and asum as for the power law, in
 // rate units (the residual then takes dt instead of dt gdot0).
-template <int TT, typename T, typename W>
-__device__ __forceinline__ void flow_type_mr(const T (&s)[6], const SysParams<T>& sp, W (&w)[12], T (&g)[6],
+template <int TT, typename T, typename W, typename SP>
+__device__ __forceinline__ void flow_type_mr(const T (&s)[6], const SP& sp, W (&w)[12], T (&g)[6],
                                              T& visc, T& asum) {
   T x[4];
   resolved_type<TT>(s, T(kUN), T(kUS), x);
@@ -355,8 +372,8 @@ __device__ __forceinline__ void flow_type_mr(const T (&s)[6], const SysParams<T>
   g[3 + slot_q(TT)] += gs0 - gs1;
 }
 
-template <typename T, typename W>
-__device__ __forceinline__ void flow_eval_mr(const T (&s)[6], const SysParams<T>& sp, W (&w)[12], T (&g)[6],
+template <typename T, typename W, typename SP>
+__device__ __forceinline__ void flow_eval_mr(const T (&s)[6], const SP& sp, W (&w)[12], T (&g)[6],
                                              T& visc, T& asum) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = T(-0.0);
@@ -398,10 +415,10 @@ __device__ __forceinline__ void cubic_mul(T d, T o, T sh, const T (&v)[6], T (&o
 // The residual is formed in T (it cancels large terms); once formed it is
 // returned in FP32 with the Jacobian weights w: the Newton direction is an
 // FP32 solve, and rounding a small residual keeps its relative precision.
-template <int FLOW, typename T>
+template <int FLOW, typename T, typename SP>
 __device__ __forceinline__ void local_residual(const Mat& M, const T (&s)[6], const T (&b)[6],
                                                T tauc, T itauc, float (&w)[12], float (&r)[6], T& phi,
-                                               const SysParams<T>& sp) {
+                                               const SP& sp) {
   T g[6], visc, asum;
   if constexpr (FLOW == FLOW_MR) flow_eval_mr(s, sp, w, g, visc, asum);
   else flow_eval<FLOW == FLOW_POWER_INT>(s, itauc, T(M.n), M.n_int, w, g, visc, asum);

@@ -171,14 +171,13 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
 #ifndef FFTEVP_LOCAL_WAVES_F32
 #define FFTEVP_LOCAL_WAVES_F32 4
 #endif
-// the paper's flow rule holds more per-system state (exp, four parameters);
-// its FP32 instance runs three waves per SIMD with a few spilled registers
-// (faster than two without: the third wave hides more latency)
+// the paper's flow rule, with its per-system parameters staged in LDS: two
+// waves per SIMD in FP64 (241 VGPRs), four in FP32 (122)
 #ifndef FFTEVP_MR_WAVES
 #define FFTEVP_MR_WAVES 1
 #endif
 #ifndef FFTEVP_MR_WAVES_F32
-#define FFTEVP_MR_WAVES_F32 3
+#define FFTEVP_MR_WAVES_F32 4
 #endif
 
 // FLOW: the flow rule (FLOW_POWER, FLOW_POWER_INT when the rate exponent is
@@ -193,8 +192,17 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
   // the block reduction
   constexpr int SH_BYTES = 3 * S::LPB * S::LS * (int)sizeof(cx<T>);
   constexpr int RED_BYTES = NPART * (S::NT + 32) * (int)sizeof(double);
-  __shared__ __align__(16) unsigned char lds[SH_BYTES > RED_BYTES ? SH_BYTES : RED_BYTES];
+  // the paper's law: per-system parameters of the thread's voxel staged in
+  // LDS after the lines, MRQ rows (the reduction reuses the space): all 36
+  // in 128-thread blocks; tau_pass and 1/tau_cut in 256-thread blocks, where
+  // 36 FP64 rows (74 KB) would leave one block per CU
+  constexpr int MRQ = FLOW != FLOW_MR ? 0 : (S::NT <= 128 ? 36 : 24);
+  constexpr bool STAGE = MRQ > 0;
+  constexpr int MRP_BYTES = MRQ * S::NT * (int)sizeof(T);
+  constexpr int LDS_BYTES = SH_BYTES + MRP_BYTES > RED_BYTES ? SH_BYTES + MRP_BYTES : RED_BYTES;
+  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
   cx<T>* sh = reinterpret_cast<cx<T>*>(lds);
+  T* mrp = reinterpret_cast<T*>(lds + SH_BYTES);
   const size_t planes = (size_t)a.n1 * a.n2;
   const size_t vox = planes * N0;
   const size_t line0 = (size_t)blockIdx.x * S::LPB;
@@ -283,6 +291,11 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
       }
     };
     if (v > 0) fetch(g);
+    if constexpr (STAGE) {
+      // each thread reads back only its own column: no barrier
+#pragma unroll
+      for (int q = 0; q < MRQ; ++q) mrp[q * S::NT + threadIdx.x] = a.sysp[(size_t)q * vox + g];
+    }
     const T tauc = T(M.tau0) + T(M.taylor) * sqrt(prho);
     const T itauc = T(1) / tauc;
 
@@ -320,14 +333,18 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
         T phi1, cand[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * T(d[k]);
-        if constexpr (FLOW == FLOW_MR && sizeof(T) == 8) {
-          // FP64: the per-system parameters are re-read (from cache) at every
-          // evaluation through a pointer made opaque per pass, instead of
-          // being hoisted out of the loop into 72 live registers (two waves
-          // per SIMD instead of one: 6 % faster; FP32 kept them, 12 % faster)
+        if constexpr (STAGE) {
+          // the per-system parameters are re-read at every evaluation (from
+          // LDS; A from cache in 256-thread blocks) through a column index
+          // and a pointer made opaque per pass, instead of being hoisted out
+          // of the loop into 36 (FP32) or 72 (FP64) live registers: at 128^3
+          // the local kernel ran 30 % (FP32) and 36 % (FP64) faster than
+          // with the parameters in registers (FP32) or re-read from cache
+          // (FP64)
           uint64_t pp = reinterpret_cast<uint64_t>(sp.p);
-          asm volatile("" : "+s"(pp));
-          const SysParams<T> spp{reinterpret_cast<const T*>(pp), sp.V, sp.g};
+          int col = threadIdx.x;
+          asm volatile("" : "+s"(pp), "+v"(col));
+          const SysParamsStaged<T, MRQ> spp{reinterpret_cast<const T*>(pp), sp.V, sp.g, mrp, S::NT, col};
           local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, spp);
         } else {
           local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, sp);

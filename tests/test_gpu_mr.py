@@ -55,6 +55,29 @@ def test_paper_law_matches_oracle(require_gpu, shape, gnd):
         assert rel(g, v) < 1e-10, (k, rel(g, v))
 
 
+# Lines of 256 and 512 points run the local kernel in 256-thread blocks,
+# which stage two of the three per-system parameter rows in LDS (all three
+# in 128-thread blocks, the cases above), and at 512 two voxels per thread.
+# Whole increments take the oracle minutes there, so the k-th iterates are
+# compared instead.
+@pytest.mark.parametrize("shape,precision", [((256, 8, 8), "fp64"), ((512, 8, 8), "fp64"), ((256, 8, 8), "mixed")])
+def test_paper_law_iterates_long_lines(require_gpu, shape, precision):
+    from paper_1509_04953_amd import Opts
+    s, o = setup(shape, 8, 44, precision=precision)
+    k = 8
+    print(f"case: paper's law iterates {shape} {precision} k={k}", flush=True)
+    r = s.step(Opts(tol=1e-14, max_iter=k))
+    assert r.iters == k
+    ro = o.increment(Loading(), tol=1e-14, max_iter=k)
+    bound = 1e-10 if precision == "fp64" else 1e-4
+    for name, v in (("sigma_iter", o.field("sigma")), ("strain_iter", o.field("strain"))):
+        err = rel(s.field(name).cpu().numpy(), v)
+        print(name, err, flush=True)
+        assert err < bound, (name, err)
+    if precision == "fp64":
+        assert abs(r.err_c - ro["err_c"]) <= 1e-8 * ro["err_c"]
+
+
 def test_paper_law_mixed_precision(require_gpu):
     from paper_1509_04953_amd import Opts
     s, o = setup((16, 16, 16), 8, 42, precision="mixed")
