@@ -11,10 +11,10 @@ namespace fftevp {
 enum { MODE_NEWTON = 0, MODE_TANGENT = 1, MODE_EXPORT = 2 };
 
 // per-block partial sums of the local kernel, stored [NPART][blocks]:
-// [0] sum |e - eps|^2, [1..6] sum sigma, [7] sum sigma:e, [8] Newton failures,
-// [9] sum Newton iterations, [10] sum line-search halvings,
-// [11] max Newton iterations (reduced by max)
-constexpr int NPART = 12;
+// [0] sum |e - eps|^2, [1..6] sum sigma, [7] Newton failures,
+// [8] sum Newton iterations, [9] sum line-search halvings,
+// [10] max Newton iterations (reduced by max)
+constexpr int NPART = 11;
 
 // Voxels per block of the local kernel (min(256, voxels) threads, one voxel
 // per thread up to 256) and x-lines per block for a line length n0 (every
@@ -37,7 +37,7 @@ __host__ __device__ constexpr int local_lines_per_block(int n0) {
 struct Ctl {
   double E[6];      // macroscopic strain (Mandel) used by the next spectral update
   double Sigma[6];  // mean stress of the latest iterate (Mandel)
-  double err_c, err_bc, se, nfail, nmax, nsum, lssum;
+  double err_c, err_bc, nfail, nmax, nsum, lssum;
   int done;         // 0 running, 1 converged, 2 non-finite
   int iters;        // completed local solves
 };

@@ -338,7 +338,7 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
           // LDS; A from cache in 256-thread blocks) through a column index
           // and a pointer made opaque per pass, instead of being hoisted out
           // of the loop into 36 (FP32) or 72 (FP64) live registers: at 128^3
-          // the local kernel ran 30 % (FP32) and 36 % (FP64) faster than
+          // the local kernel takes 29 % (FP32) and 37 % (FP64) less time than
           // with the parameters in registers (FP32) or re-read from cache
           // (FP64)
           uint64_t pp = reinterpret_cast<uint64_t>(sp.p);
@@ -449,19 +449,17 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
 #pragma unroll
     for (int p = 0; p < 3; ++p) sh[(p * S::LPB + l) * S::LS + x] = {tau[2 * p], tau[2 * p + 1]};
 
-    double e2 = 0.0, se = 0.0;
+    double e2 = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       e2 += (double)err[k] * (double)err[k];
-      se += (double)sig[k] * (double)e[k];
       part[1 + k] += (double)sig[k];
     }
     part[0] += e2;
-    part[7] += se;
-    part[8] += (double)fail;
-    part[9] += (double)nit;
-    part[10] += (double)nls;
-    part[11] = fmax(part[11], (double)nit);
+    part[7] += (double)fail;
+    part[8] += (double)nit;
+    part[9] += (double)nls;
+    part[10] = fmax(part[10], (double)nit);
   }
   __syncthreads();
   fft_lines<T, N0, false, 3 * S::LPB, S::LS, S::NT>(sh, a.tw);
@@ -941,11 +939,10 @@ __device__ void finalize_sums(const FinArgs& a, Ctl* ctl, const double (&tot)[NP
   for (int k = 0; k < 6; ++k) ctl->Sigma[k] = Sig[k];
   ctl->err_c = err_c;
   ctl->err_bc = err_bc;
-  ctl->se = tot[7] * iv;
-  ctl->nfail = tot[8];
-  ctl->nsum = tot[9];
-  ctl->lssum = tot[10];
-  ctl->nmax = tot[11];
+  ctl->nfail = tot[7];
+  ctl->nsum = tot[8];
+  ctl->lssum = tot[9];
+  ctl->nmax = tot[10];
   ctl->iters += 1;
   if (!isfinite(err_c) || isnan(err_bc) || !isfinite(nS)) {
     ctl->done = 2;
