@@ -92,6 +92,18 @@ struct SysParamsStaged {
   }
 };
 
+// tau_pass and A staged in LDS (rows 0-11 and 12-23 of stride ls), 1/tau_cut
+// held in registers
+template <typename T>
+struct SysParamsHybrid {
+  const T* l;
+  int ls, t;
+  const T (&ir)[12];
+  __device__ __forceinline__ T tp(int a) const { return l[a * ls + t]; }
+  __device__ __forceinline__ T itc(int a) const { return ir[a]; }
+  __device__ __forceinline__ T amp(int a) const { return l[(12 + a) * ls + t]; }
+};
+
 // 1/x: the hardware reciprocal, refined once by Newton's method in FP64
 __device__ __forceinline__ float fast_recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_recip(double x) {

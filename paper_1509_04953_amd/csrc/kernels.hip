@@ -172,19 +172,30 @@ __device__ __forceinline__ void load_packed(const cx<T>* __restrict__ main, cons
 #define FFTEVP_LOCAL_WAVES_F32 4
 #endif
 // the paper's flow rule, with its per-system parameters staged in LDS: two
-// waves per SIMD in FP64 (241 VGPRs), four in FP32 (122)
+// waves per SIMD in FP64 (256 VGPRs with 10 spilled in 128-thread blocks),
+// four in FP32 (122)
 #ifndef FFTEVP_MR_WAVES
-#define FFTEVP_MR_WAVES 1
+#define FFTEVP_MR_WAVES 2
 #endif
 #ifndef FFTEVP_MR_WAVES_F32
 #define FFTEVP_MR_WAVES_F32 4
 #endif
 
+// waves per SIMD the local kernel is compiled for; with two voxels per
+// thread (lines of 512 points) the targets at which it does not spill (one
+// wave FP64, three FP32)
+template <typename T, int N0, int FLOW>
+__host__ __device__ constexpr int local_waves() {
+  if (LocalShape<T, N0>::VPT > 1) return sizeof(T) == 8 ? 1 : 3;
+  if (FLOW == FLOW_MR) return sizeof(T) == 8 ? FFTEVP_MR_WAVES : FFTEVP_MR_WAVES_F32;
+  return sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32;
+}
+
 // FLOW: the flow rule (FLOW_POWER, FLOW_POWER_INT when the rate exponent is
 // a positive integer, FLOW_MR for the paper's law; the host picks the
 // instance).
 template <typename T, int N0, int MODE, int FLOW>
-__global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(T) == 8 ? FFTEVP_MR_WAVES : FFTEVP_MR_WAVES_F32) : (sizeof(T) == 8 ? FFTEVP_LOCAL_WAVES : FFTEVP_LOCAL_WAVES_F32)) void k_local(
+__global__ __launch_bounds__((LocalShape<T, N0>::NT), (local_waves<T, N0, FLOW>())) void k_local(
     LocalArgs<T> a) {
   using S = LocalShape<T, N0>;
   if (a.ctl && a.ctl->done) return;
@@ -193,10 +204,14 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
   constexpr int SH_BYTES = 3 * S::LPB * S::LS * (int)sizeof(cx<T>);
   constexpr int RED_BYTES = NPART * (S::NT + 32) * (int)sizeof(double);
   // the paper's law: per-system parameters of the thread's voxel staged in
-  // LDS after the lines, MRQ rows (the reduction reuses the space): all 36
-  // in 128-thread blocks; tau_pass and 1/tau_cut in 256-thread blocks, where
-  // 36 FP64 rows (74 KB) would leave one block per CU
-  constexpr int MRQ = FLOW != FLOW_MR ? 0 : (S::NT <= 128 ? 36 : 24);
+  // LDS after the lines, MRQ rows (the reduction reuses the space). FP32 in
+  // 128-thread blocks: all 36. FP64 in 128-thread blocks (HYB): tau_pass and
+  // A, with 1/tau_cut in 24 registers, so that four blocks fit a CU (31 KB
+  // each; all 36 rows, 43 KB, fit three: 12 % slower). 256-thread blocks:
+  // tau_pass and 1/tau_cut, A read from cache (36 FP64 rows, 74 KB, would
+  // leave one block per CU)
+  constexpr bool HYB = FLOW == FLOW_MR && sizeof(T) == 8 && S::NT <= 128;
+  constexpr int MRQ = FLOW != FLOW_MR ? 0 : (HYB ? 24 : (S::NT <= 128 ? 36 : 24));
   constexpr bool STAGE = MRQ > 0;
   constexpr int MRP_BYTES = MRQ * S::NT * (int)sizeof(T);
   constexpr int LDS_BYTES = SH_BYTES + MRP_BYTES > RED_BYTES ? SH_BYTES + MRP_BYTES : RED_BYTES;
@@ -294,7 +309,8 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
     if constexpr (STAGE) {
       // each thread reads back only its own column: no barrier
 #pragma unroll
-      for (int q = 0; q < MRQ; ++q) mrp[q * S::NT + threadIdx.x] = a.sysp[(size_t)q * vox + g];
+      for (int q = 0; q < MRQ; ++q)
+        mrp[q * S::NT + threadIdx.x] = a.sysp[(size_t)(HYB && q >= 12 ? q + 12 : q) * vox + g];
     }
     const T tauc = T(M.tau0) + T(M.taylor) * sqrt(prho);
     const T itauc = T(1) / tauc;
@@ -324,6 +340,11 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
       T step = T(0);
       const float cj = FLOW == FLOW_MR ? float(M.dt) : float(T(M.c1) * T(M.n) * itauc);
       const SysParams<T> sp{a.sysp, vox, g};
+      T itcr[12];
+      if constexpr (HYB) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) itcr[q] = sp.itc(q);
+      }
       const T ntol2 = T(M.ntol) * T(M.ntol), qtol2 = T(M.qtol) * T(M.qtol);
       bool conv = false, first = true;
 #pragma unroll
@@ -344,8 +365,13 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), FLOW == FLOW_MR ? (sizeof(
           uint64_t pp = reinterpret_cast<uint64_t>(sp.p);
           int col = threadIdx.x;
           asm volatile("" : "+s"(pp), "+v"(col));
-          const SysParamsStaged<T, MRQ> spp{reinterpret_cast<const T*>(pp), sp.V, sp.g, mrp, S::NT, col};
-          local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, spp);
+          if constexpr (HYB) {
+            const SysParamsHybrid<T> spp{mrp, S::NT, col, itcr};
+            local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, spp);
+          } else {
+            const SysParamsStaged<T, MRQ> spp{reinterpret_cast<const T*>(pp), sp.V, sp.g, mrp, S::NT, col};
+            local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, spp);
+          }
         } else {
           local_residual<FLOW>(M, cand, b, tauc, itauc, w, r, phi1, sp);
         }
