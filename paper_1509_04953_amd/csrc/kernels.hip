@@ -356,12 +356,12 @@ __global__ __launch_bounds__((LocalShape<T, N0>::NT), (local_waves<T, N0, FLOW>(
         for (int k = 0; k < 6; ++k) cand[k] = sc[k] + step * T(d[k]);
         if constexpr (STAGE) {
           // the per-system parameters are re-read at every evaluation (from
-          // LDS; A from cache in 256-thread blocks) through a column index
-          // and a pointer made opaque per pass, instead of being hoisted out
-          // of the loop into 36 (FP32) or 72 (FP64) live registers: at 128^3
-          // the local kernel takes 29 % (FP32) and 37 % (FP64) less time than
-          // with the parameters in registers (FP32) or re-read from cache
-          // (FP64)
+          // LDS; 1/tau_cut from registers in FP64 128-thread blocks, A from
+          // cache in 256-thread blocks) through a column index and a pointer
+          // made opaque per pass, instead of being hoisted out of the loop
+          // into 36 (FP32) or 72 (FP64) live registers: at 128^3 the local
+          // kernel takes 29 % (FP32) and 44 % (FP64) less time than with the
+          // parameters in registers (FP32) or re-read from cache (FP64)
           uint64_t pp = reinterpret_cast<uint64_t>(sp.p);
           int col = threadIdx.x;
           asm volatile("" : "+s"(pp), "+v"(col));
